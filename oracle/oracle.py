@@ -1,0 +1,196 @@
+"""Python access to the CPU oracle (liboracle_rf.so): TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg may
+import this module.  It compiles ``oracle_rf.c`` with gcc on first use (no GPU,
+no HIP, nothing shared with the library under test) and wraps its functions with
+NumPy arrays.  Every function follows the readings documented in
+``oracle_rf.c``; see that file for the method's steps and citations.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle_rf.c")
+LIB = os.path.join(HERE, "liboracle_rf.so")
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+OK, EINVAL, ERANGE, ENOMEM = 0, -1, -2, -3
+LEAF = 255
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"{what} failed with code {rc}")
+        self.rc = rc
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (idempotent unless forced)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "oracle_rf.h"))):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def configure(L):
+    """Declare the C signatures on a loaded oracle library and return it."""
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.oracle_philox4x64_10.argtypes = [P, P, P]
+    L.oracle_philox4x64_10.restype = None
+    L.oracle_rf_bin.argtypes = [P, P, i64, i32, i32, i32, P, P, P]
+    L.oracle_rf_bin_apply.argtypes = [P, P, i64, i32, i32, P, P, P]
+    L.oracle_rf_y_fixed.argtypes = [P, i64, P]
+    L.oracle_rf_fit.argtypes = [P, i64, i32, P, P, P, i64, P, i32, i32, i64, P, P, P, P, P, P, i32]
+    L.oracle_rf_predict.argtypes = [P, i64, i32, i32, i64, P, P, P, P, P, P]
+    for f in ("oracle_rf_bin", "oracle_rf_bin_apply", "oracle_rf_y_fixed", "oracle_rf_fit",
+              "oracle_rf_predict"):
+        getattr(L, f).restype = ctypes.c_int
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = configure(ctypes.CDLL(LIB))
+    return _lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("num_trees", ctypes.c_int32), ("mtry", ctypes.c_int32), ("min_node_size", ctypes.c_int32),
+                ("bootstrap", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+def philox(counter, key) -> np.ndarray:
+    """One Philox4x64-10 block for a 4-word counter and a 2-word key."""
+    c = np.asarray(counter, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().oracle_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+@dataclass
+class Binning:
+    thresholds: np.ndarray  # float32 [p, 255]
+    n_bins: np.ndarray  # int32 [p + 1]
+    codes: np.ndarray  # uint8 [n, p + 1]
+
+    def column_thresholds(self, j: int) -> np.ndarray:
+        return self.thresholds[j, : self.n_bins[j] - 1]
+
+
+def bin(X: np.ndarray, device: np.ndarray, n_devices: int, max_bins: int) -> Binning:
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    device = np.ascontiguousarray(device, dtype=np.int32)
+    n, p = X.shape
+    thr = np.zeros((p, 255), dtype=np.float32)
+    nb = np.zeros(p + 1, dtype=np.int32)
+    codes = np.zeros((n, p + 1), dtype=np.uint8)
+    _check(lib().oracle_rf_bin(_p(X), _p(device), n, p, n_devices, max_bins, _p(thr), _p(nb), _p(codes)),
+           "oracle_rf_bin")
+    return Binning(thr, nb, codes)
+
+
+def bin_apply(b: Binning, X: np.ndarray, device: np.ndarray, n_devices: int) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    device = np.ascontiguousarray(device, dtype=np.int32)
+    n, p = X.shape
+    codes = np.zeros((n, p + 1), dtype=np.uint8)
+    _check(lib().oracle_rf_bin_apply(_p(X), _p(device), n, p, n_devices, _p(b.thresholds), _p(b.n_bins),
+                                     _p(codes)), "oracle_rf_bin_apply")
+    return codes
+
+
+def y_fixed(y: np.ndarray) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(y.shape[0], dtype=np.int64)
+    _check(lib().oracle_rf_y_fixed(_p(y), y.shape[0], _p(out)), "oracle_rf_y_fixed")
+    return out
+
+
+@dataclass
+class Forest:
+    """Trees [tree_begin, tree_end) of one forest, each in a slot of `capacity` nodes."""
+
+    num_trees: int
+    tree_begin: int
+    capacity: int
+    col: np.ndarray
+    bin: np.ndarray
+    left: np.ndarray
+    q: np.ndarray
+    N: np.ndarray
+    n_nodes: np.ndarray
+
+    def tree(self, t: int) -> dict:
+        """Node arrays of tree t (breadth-first order), trimmed to its node count."""
+        s = (t - self.tree_begin) * self.capacity
+        k = int(self.n_nodes[t - self.tree_begin])
+        return {"col": self.col[s:s + k], "bin": self.bin[s:s + k], "left": self.left[s:s + k],
+                "q": self.q[s:s + k], "N": self.N[s:s + k]}
+
+
+def fit(codes: np.ndarray, n_bins: np.ndarray, y: np.ndarray, num_trees: int, mtry: int, min_node_size: int,
+        seed: int = 1, bootstrap: bool = True, train_rows: np.ndarray | None = None, trees=None,
+        n_threads: int = 0) -> Forest:
+    """Grow trees `trees` (a range; default all) of a forest on the given code matrix."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    n, C = codes.shape
+    n_bins = np.ascontiguousarray(n_bins, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
+    n_train = n if tr is None else tr.shape[0]
+    if trees is None:
+        trees = range(num_trees)
+    t0, t1 = trees.start, trees.stop
+    cap = max(1, 2 * n_train - 1)
+    k = t1 - t0
+    col = np.zeros(k * cap, np.uint8)
+    bn = np.zeros(k * cap, np.uint8)
+    left = np.zeros(k * cap, np.int32)
+    q = np.zeros(k * cap, np.int64)
+    N = np.zeros(k * cap, np.int32)
+    nn = np.zeros(k, np.int64)
+    prm = Params(num_trees, mtry, min_node_size, 1 if bootstrap else 0, seed)
+    _check(lib().oracle_rf_fit(_p(codes), n, C, _p(n_bins), _p(y), _p(tr), n_train, ctypes.byref(prm), t0, t1,
+                               cap, _p(col), _p(bn), _p(left), _p(q), _p(N), _p(nn), n_threads),
+           "oracle_rf_fit")
+    return Forest(num_trees, t0, cap, col, bn, left, q, N, nn)
+
+
+def predict(forest: Forest, codes: np.ndarray):
+    """(P, yhat): int64 leaf sums over the forest's trees and the forest mean.
+
+    The mean divides by the number of trees held (the whole forest when all trees
+    were grown)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    m, C = codes.shape
+    k = forest.n_nodes.shape[0]
+    P = np.zeros(m, np.int64)
+    yhat = np.zeros(m, np.float64)
+    _check(lib().oracle_rf_predict(_p(codes), m, C, k, forest.capacity, _p(forest.col), _p(forest.bin),
+                                   _p(forest.left), _p(forest.q), _p(P), _p(yhat)), "oracle_rf_predict")
+    return P, yhat
