@@ -1,0 +1,211 @@
+/*
+ * aiwc_rf.h -- C ABI of the MI355X (gfx950) random-forest performance model.
+ *
+ * The model is the one of Sec. III-B of "OpenCL Performance Prediction using
+ * Architecture-Independent Features" (Johnston & Milthorpe, 2018): a random-forest
+ * regression that maps the AIWC feature vector of an OpenCL kernel (Table I) plus
+ * the device it runs on (Table II) to its execution time, with the three ranger
+ * parameters num.trees, mtry and min.node.size.  The calls follow the problem as
+ * the paper states it (Abstract; Sec. I; Sec. VI): features and a device id in,
+ * a predicted execution time out; fitting happens once, querying is cheap.
+ *
+ * Conventions shared by every call:
+ *   - Return value: AIWC_RF_OK (0) or a negative AIWC_RF_E* code.  The message of
+ *     the last failure on the calling thread is returned by aiwc_rf_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Array arguments are DEVICE pointers (hipMalloc'ed or any device tensor's
+ *     storage) unless the argument name ends in _host.  Device arrays must live on
+ *     the current HIP device.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work
+ *     is enqueued on it; a call returns once its results are complete unless the
+ *     call says otherwise.
+ *   - Handles are opaque, owned by the library and released with the matching
+ *     *_free call.  Outputs are caller-allocated.  A fitted forest is immutable, so
+ *     predictions from several threads and streams may run concurrently.
+ *
+ * Numerical contract (identical, bit for bit, to the separate CPU oracle):
+ *   - the response y (log10 seconds) is carried as int64 fixed point
+ *     y_fp = rint(y * 2^16); |y| <= 64 is required;
+ *   - node sums of weight N, response S and squared response Q are exact integers;
+ *   - a split maximises S_L^2/N_L + S_R^2/N_R (variance reduction) evaluated in
+ *     IEEE binary64 without contraction; ties keep the lowest (column, bin);
+ *   - a leaf holds its mean as q = round-half-away(S * 2^16 / N) (units 2^-32);
+ *     the prediction is (sum of q over trees) * 2^-32 / num.trees, one rounding.
+ */
+#ifndef AIWC_RF_H
+#define AIWC_RF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define AIWC_RF_OK 0
+#define AIWC_RF_EINVAL (-1) /* bad argument: null pointer, size or parameter out of range, NaN feature */
+#define AIWC_RF_ERANGE (-2) /* response non-finite or |y| > 64, or an internal capacity limit hit */
+#define AIWC_RF_ENOMEM (-3) /* device or host allocation failed, or a memory budget would be exceeded */
+#define AIWC_RF_EHIP (-4)   /* a HIP runtime call failed; the message carries HIP's error string */
+#define AIWC_RF_ESTATE (-5) /* handle used in a state that does not allow the call */
+
+/* Limits.  Rows: the fixed-point budget keeps |S| <= 2^40 and Q <= 2^62 exact. */
+#define AIWC_RF_MAX_ROWS (1 << 18)
+#define AIWC_RF_MAX_FEATURES 255
+#define AIWC_RF_MAX_BINS 256
+#define AIWC_RF_MAX_TREES (1 << 14)
+#define AIWC_RF_LEAF 255 /* column value that marks a leaf in exported node arrays */
+
+typedef struct aiwc_rf_binner aiwc_rf_binner; /* per-column thresholds and bin counts */
+typedef struct aiwc_rf_forest aiwc_rf_forest; /* one or many fitted forests, device resident */
+
+/* The three model parameters of Sec. III-B (num.trees, mtry, min.node.size), the
+ * bootstrap switch and the seed of the Philox4x64-10 streams that draw the
+ * bootstrap sample (counter (block, 0, 0, tree)) and each node's mtry candidate
+ * columns (counter (block, 1, node, tree)), key (seed, 0). */
+typedef struct {
+  int32_t num_trees;     /* 1 .. AIWC_RF_MAX_TREES */
+  int32_t mtry;          /* 1 .. number of code columns (features + device) */
+  int32_t min_node_size; /* >= 1; a node whose bootstrap weight is <= this is a leaf */
+  int32_t bootstrap;     /* 1: each tree draws n rows with replacement; 0: each row once */
+  uint64_t seed;
+} aiwc_rf_params;
+
+/* ------------------------------------------------------------------------------
+ * Binning.  Turns the AIWC feature matrix (Table I metrics; the paper uses 34 of
+ * them, Sec. III-B) and the device id (Table II) into uint8 codes.
+ *
+ * X:         n x p float32, row-major (device).
+ * device_id: n int32 in [0, n_devices) (device).
+ * codes:     n x (p + 1) uint8, row-major, output (device); column p = device id.
+ * *binner:   NULL on entry -> thresholds are fitted on these rows and a new binner
+ *            is returned in *binner; non-NULL -> its thresholds are applied.
+ * Thresholds per feature column: if the column has at most max_bins distinct
+ * values, every distinct value but the largest (lossless); otherwise the order
+ * statistics s[floor(k n / max_bins) - 1], k = 1 .. max_bins - 1, of the sorted
+ * column, repeats and values not below the column maximum dropped.  code(x) = the
+ * number of thresholds strictly below x (-0.0 is treated as +0.0).
+ * Errors: EINVAL for null pointers, n outside [1, AIWC_RF_MAX_ROWS], p outside
+ * [1, 255], n_devices outside [1, 256], max_bins outside [2, 256], a NaN feature or
+ * a device id out of range; EINVAL also if an applied binner has another p.
+ * Synchronous. */
+int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, int32_t n_devices,
+                int32_t max_bins, aiwc_rf_binner** binner, uint8_t* codes, void* stream);
+
+/* A binner that only carries bin counts (n_bins_host[n_cols], each in [1, 256]),
+ * for fitting code matrices that were binned elsewhere.  It cannot bin features. */
+int aiwc_rf_binner_from_counts(const int32_t* n_bins_host, int32_t n_cols, aiwc_rf_binner** binner);
+
+/* Copy out p, n_devices, the bin count of each of the p + 1 columns and the
+ * thresholds (p x 255 float32, column j's list first, unused slots 0).  Any output
+ * pointer may be NULL.  thresholds_host must be NULL for a counts-only binner. */
+int aiwc_rf_binner_export_host(const aiwc_rf_binner* binner, int32_t* p_host, int32_t* n_devices_host,
+                               int32_t* n_bins_host, float* thresholds_host);
+void aiwc_rf_binner_free(aiwc_rf_binner* binner);
+
+/* ------------------------------------------------------------------------------
+ * Fitting (Sec. III-B, and the tuning grids of Sec. III-B/III-C).
+ *
+ * codes:        n x n_cols uint8 row-major (device); every code < the binner's
+ *               bin count of its column.
+ * y_log10:      n float64 (device): log10 execution time of each row.
+ * params_host:  n_forests parameter sets.
+ * n_forests==1: one forest on the rows selected below.
+ * n_forests >1: a grid; forest k trains on params_host[k] and on the rows whose
+ *               fold differs from heldout_fold_host[k].
+ * fold_id:      n int8 (device) fold of each row, -1 = always trained on; may be
+ *               NULL when no heldout_fold_host entry is >= 0.
+ * heldout_fold_host: n_forests ints (host) or NULL (= all -1 = train on all rows).
+ * flags:        AIWC_RF_FIT_* below.
+ * *forest:      receives a new forest handle.
+ * Each forest's tree t grows from the Philox streams keyed by (seed, t), so a tree
+ * depends only on its training rows, its parameters and (seed, t).
+ * Errors: EINVAL for bad sizes/parameters/codes, ERANGE for a response outside
+ * [-64, 64] or non-finite, ENOMEM when the node pool or scratch cannot be
+ * allocated.  Synchronous unless AIWC_RF_FIT_ASYNC is given. */
+#define AIWC_RF_FIT_FUSED 0u /* grid: every tree of every forest in one persistent launch, captured in a hipGraph */
+#define AIWC_RF_FIT_PLAIN 1u /* grid: one launch sequence per forest (same results) */
+#define AIWC_RF_FIT_ASYNC 2u /* return after enqueueing; aiwc_rf_forest_wait() reports the status */
+int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                const double* y_log10, const int8_t* fold_id, const aiwc_rf_params* params_host,
+                const int32_t* heldout_fold_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,
+                void* stream);
+
+/* Wait for an ASYNC fit and return its status (OK, ERANGE, EINVAL). */
+int aiwc_rf_forest_wait(const aiwc_rf_forest* forest);
+
+/* Number of forests, code columns and trees of forest forest_index. */
+int aiwc_rf_forest_info(const aiwc_rf_forest* forest, int32_t forest_index, int32_t* n_forests_host,
+                        int32_t* n_cols_host, int32_t* num_trees_host, int64_t* total_nodes_host);
+
+/* Node counts of trees [tree_begin, tree_end) of a forest (n_nodes_host[tree_end - tree_begin]). */
+int aiwc_rf_forest_tree_sizes(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
+                              int32_t tree_end, int64_t* n_nodes_host);
+
+/* Node arrays of trees [tree_begin, tree_end), concatenated in tree order, each tree
+ * in breadth-first node order (root = 0; the children of a split node are left and
+ * left + 1).  col: split column or AIWC_RF_LEAF; bin: rows with code <= bin go
+ * left; left: child id within the tree (-1 for leaves); q: leaf value in units of
+ * 2^-32 (0 for split nodes); N: bootstrap weight of the node.  Arrays hold the sum
+ * of the node counts; any may be NULL. */
+int aiwc_rf_forest_export_host(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
+                               int32_t tree_end, uint8_t* col_host, uint8_t* bin_host, int32_t* left_host,
+                               int64_t* q_host, int32_t* N_host);
+void aiwc_rf_forest_free(aiwc_rf_forest* forest);
+
+/* ------------------------------------------------------------------------------
+ * Prediction (the query of Sec. I and Sec. VI: AIWC features + device -> time).
+ *
+ * codes:       n x n_cols uint8 row-major (device), binned with the fit's binner.
+ * y_log10_out: n float64 (device): predicted log10 execution time.
+ * Asynchronous on `stream`: the output is ready when the stream reaches it.
+ * Errors: EINVAL for a bad forest_index, n < 0 or null pointers. */
+int aiwc_rf_predict(const aiwc_rf_forest* forest, int32_t forest_index, const uint8_t* codes, int64_t n,
+                    double* y_log10_out, void* stream);
+
+/* Exact partial sums: sum_out[i] = sum over trees [tree_begin, tree_end) of the
+ * leaf value reached by row i (int64, units 2^-32).  Sums of disjoint tree ranges
+ * add up exactly, so a forest split across devices recombines bit for bit. */
+int aiwc_rf_predict_sum(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
+                        int32_t tree_end, const uint8_t* codes, int64_t n, int64_t* sum_out, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Serving (the scheduler-facing use of Sec. VI): a resident forest answers a
+ * stream of prediction requests of different sizes.  Requests are admitted while
+ * their staging memory fits the budget, packed into batches as they arrive
+ * (continuous batching) and run on several streams so that copies and kernels of
+ * different batches overlap.  Each answer equals what aiwc_rf_predict returns for
+ * the same rows alone.
+ *
+ * create:  forest/forest_index to serve; memory_budget_bytes caps the device and
+ *          pinned staging held by admitted requests (each row costs n_cols + 8
+ *          bytes); max_batch_rows caps one batch; n_streams in [1, 8].
+ * submit:  codes_host is n x n_cols uint8, out_host receives n float64; both stay
+ *          owned by the caller and must stay valid until the request completes.
+ *          Never blocks; returns the request's ticket.  ENOMEM if n rows alone
+ *          exceed the budget or max_batch_rows.
+ * poll:    copies up to max_tickets completed tickets (completion order) and their
+ *          latency in seconds (submit -> results in out_host); *n_done receives the
+ *          count.
+ * drain:   blocks until every submitted request has completed.
+ * stats:   rows served, batches launched, peak admitted bytes. */
+typedef struct aiwc_rf_server aiwc_rf_server;
+int aiwc_rf_server_create(const aiwc_rf_forest* forest, int32_t forest_index, int64_t memory_budget_bytes,
+                          int32_t max_batch_rows, int32_t n_streams, aiwc_rf_server** server);
+int aiwc_rf_server_submit(aiwc_rf_server* server, const uint8_t* codes_host, int64_t n, double* out_host,
+                          int64_t* ticket_host);
+int aiwc_rf_server_poll(aiwc_rf_server* server, int64_t* tickets_host, double* latency_s_host,
+                        int32_t max_tickets, int32_t* n_done_host);
+int aiwc_rf_server_drain(aiwc_rf_server* server);
+int aiwc_rf_server_stats(const aiwc_rf_server* server, int64_t* rows_host, int64_t* batches_host,
+                         int64_t* peak_bytes_host);
+void aiwc_rf_server_free(aiwc_rf_server* server);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* aiwc_rf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

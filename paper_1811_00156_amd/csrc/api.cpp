@@ -1,0 +1,509 @@
+// The C ABI of libaiwc_rf (declared in include/aiwc_rf.h): argument checks,
+// handle management and the orchestration of the binning, fitting and
+// prediction kernels.  Nothing here computes a result on the host.
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <set>
+
+#include "device.h"
+#include "internal.h"
+
+using namespace aiwc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return AIWC_RF_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return AIWC_RF_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return AIWC_RF_EINVAL;
+  }
+}
+
+void require(bool ok, const char* what) {
+  if (!ok) fail(AIWC_RF_EINVAL, what);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int32_t status_to_code(uint32_t st, std::string& msg) {
+  if (st & kStatusBadY) {
+    msg = "response is non-finite or outside [-64, 64] (log10 seconds)";
+    return AIWC_RF_ERANGE;
+  }
+  if (st & kStatusBadCode) {
+    msg = "a code is not below its column's bin count";
+    return AIWC_RF_EINVAL;
+  }
+  if (st & kStatusBadFeature) {
+    msg = "a feature value is NaN";
+    return AIWC_RF_EINVAL;
+  }
+  if (st & kStatusBadDevice) {
+    msg = "a device id is outside [0, n_devices)";
+    return AIWC_RF_EINVAL;
+  }
+  if (st & kStatusCapacity) {
+    msg = "tree node capacity exceeded";
+    return AIWC_RF_ERANGE;
+  }
+  return AIWC_RF_OK;
+}
+
+GrowConfig grow_config(int64_t n_cap) {
+  GrowConfig cfg;
+  cfg.block = n_cap > 16384 ? 1024 : 512;
+  if (const char* e = std::getenv("AIWC_RF_GROW_BLOCK")) cfg.block = std::atoi(e);
+  if (const char* e = std::getenv("AIWC_RF_GROW_WG_PER_CU")) cfg.wg_per_cu = std::atoi(e);
+  return cfg;
+}
+
+// Node arrays of one tree, unpacked from the node words.
+void unpack_nodes(const std::vector<uint64_t>& words, const std::vector<uint32_t>& N, size_t count, uint8_t* col,
+                  uint8_t* bin, int32_t* left, int64_t* q, int32_t* Nout) {
+  for (size_t i = 0; i < count; ++i) {
+    const uint64_t v = words[i];
+    const bool leaf = node_col(v) == kLeafCol;
+    if (col) col[i] = (uint8_t)node_col(v);
+    if (bin) bin[i] = leaf ? 0 : (uint8_t)node_bin(v);
+    if (left) left[i] = leaf ? -1 : (int32_t)node_left(v);
+    if (q) q[i] = leaf ? node_q(v) : 0;
+    if (Nout) Nout[i] = (int32_t)N[i];
+  }
+}
+
+void check_forest(const aiwc_rf_forest* f, int32_t forest_index) {
+  require(f != nullptr, "forest is NULL");
+  require(forest_index >= 0 && forest_index < (int32_t)f->params.size(), "forest_index out of range");
+}
+
+int32_t resolve_status(const aiwc_rf_forest* fc, std::string& msg) {
+  aiwc_rf_forest* f = const_cast<aiwc_rf_forest*>(fc);
+  if (!f->waited) {
+    AIWC_HIP(hipEventSynchronize(f->done));
+    f->fit_status = status_to_code(*f->status_host, msg);
+    f->waited = true;
+    return f->fit_status;
+  }
+  status_to_code(*f->status_host, msg);
+  return f->fit_status;
+}
+
+// Traversal trusts the node words, so it only runs on a forest whose fit
+// finished without error (waits for an asynchronous fit).
+void require_fitted(const aiwc_rf_forest* f) {
+  std::string msg;
+  if (resolve_status(f, msg) != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "forest fit failed: " + msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aiwc_rf_last_error(void) { return g_last_error.c_str(); }
+
+int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, int32_t n_devices, int32_t max_bins,
+                aiwc_rf_binner** binner, uint8_t* codes, void* stream) {
+  return guard([&] {
+    require(X && device_id && codes && binner, "null pointer argument");
+    require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
+    require(p >= 1 && p <= AIWC_RF_MAX_FEATURES, "p must be in [1, 255]");
+    require(n_devices >= 1 && n_devices <= 256, "n_devices must be in [1, 256]");
+    hipStream_t s = as_stream(stream);
+    const bool fit = *binner == nullptr;
+    std::unique_ptr<aiwc_rf_binner> fresh;
+    aiwc_rf_binner* b = *binner;
+    if (fit) {
+      require(max_bins >= 2 && max_bins <= AIWC_RF_MAX_BINS, "max_bins must be in [2, 256]");
+      fresh.reset(new aiwc_rf_binner());
+      b = fresh.get();
+      AIWC_HIP(hipGetDevice(&b->device));
+      b->p = p;
+      b->n_devices = n_devices;
+      b->max_bins = max_bins;
+      b->has_thresholds = true;
+      b->n_bins.assign(p + 1, 0);
+      b->thresholds.assign((size_t)p * 255, 0.0f);
+      b->d_n_bins.reset(p + 1, s);
+      b->d_thresholds.reset((size_t)p * 255, s);
+    } else {
+      require(b->has_thresholds, "binner carries no thresholds");
+      require(b->p == p, "binner was fitted on another number of features");
+      require(b->n_devices == n_devices, "binner was fitted with another number of devices");
+    }
+    DevBuf<uint32_t> status(1, s);
+    launch_init(status.p, nullptr, s);
+    if (fit) {
+      launch_bin_fit(X, device_id, n, p, n_devices, max_bins, b->d_n_bins.p, b->d_thresholds.p, status.p, s);
+      launch_set_i32(b->d_n_bins.p + p, n_devices, s);
+    }
+    launch_bin_encode(X, device_id, n, p, n_devices, b->d_n_bins.p, b->d_thresholds.p, codes, status.p, s);
+    uint32_t st = 0;
+    AIWC_HIP(hipMemcpyAsync(&st, status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (fit) {
+      AIWC_HIP(hipMemcpyAsync(b->n_bins.data(), b->d_n_bins.p, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s));
+      AIWC_HIP(hipMemcpyAsync(b->thresholds.data(), b->d_thresholds.p, sizeof(float) * (size_t)p * 255,
+                              hipMemcpyDeviceToHost, s));
+    }
+    AIWC_HIP(hipStreamSynchronize(s));
+    std::string msg;
+    const int32_t code = status_to_code(st, msg);
+    if (code != AIWC_RF_OK) fail(code, msg);
+    if (fit) *binner = fresh.release();
+  });
+}
+
+int aiwc_rf_binner_from_counts(const int32_t* n_bins_host, int32_t n_cols, aiwc_rf_binner** binner) {
+  return guard([&] {
+    require(n_bins_host && binner, "null pointer argument");
+    require(n_cols >= 1 && n_cols <= 256, "n_cols must be in [1, 256]");
+    for (int32_t c = 0; c < n_cols; ++c) require(n_bins_host[c] >= 1 && n_bins_host[c] <= 256, "bin count outside [1, 256]");
+    std::unique_ptr<aiwc_rf_binner> b(new aiwc_rf_binner());
+    AIWC_HIP(hipGetDevice(&b->device));
+    b->p = n_cols - 1;
+    b->n_devices = n_bins_host[n_cols - 1];
+    b->has_thresholds = false;
+    b->n_bins.assign(n_bins_host, n_bins_host + n_cols);
+    b->d_n_bins.reset(n_cols, nullptr);
+    AIWC_HIP(hipMemcpy(b->d_n_bins.p, n_bins_host, sizeof(int32_t) * n_cols, hipMemcpyHostToDevice));
+    *binner = b.release();
+  });
+}
+
+int aiwc_rf_binner_export_host(const aiwc_rf_binner* b, int32_t* p_host, int32_t* n_devices_host, int32_t* n_bins_host,
+                               float* thresholds_host) {
+  return guard([&] {
+    require(b != nullptr, "binner is NULL");
+    if (p_host) *p_host = b->p;
+    if (n_devices_host) *n_devices_host = b->n_devices;
+    if (n_bins_host) std::memcpy(n_bins_host, b->n_bins.data(), sizeof(int32_t) * b->n_bins.size());
+    if (thresholds_host) {
+      require(b->has_thresholds, "binner carries no thresholds");
+      std::memcpy(thresholds_host, b->thresholds.data(), sizeof(float) * b->thresholds.size());
+    }
+  });
+}
+
+void aiwc_rf_binner_free(aiwc_rf_binner* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  delete b;
+}
+
+int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner, const double* y_log10,
+                const int8_t* fold_id, const aiwc_rf_params* params_host, const int32_t* heldout_fold_host,
+                int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest, void* stream) {
+  return guard([&] {
+    require(codes && binner && y_log10 && params_host && forest, "null pointer argument");
+    require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
+    require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
+            "n_cols must equal the binner's column count");
+    require(n_forests >= 1, "n_forests must be >= 1");
+    require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC)) == 0, "unknown flag");
+    hipStream_t s = as_stream(stream);
+    bool need_folds = false;
+    int64_t total_trees = 0;
+    int32_t mtry_max = 1;
+    for (int32_t f = 0; f < n_forests; ++f) {
+      const aiwc_rf_params& P = params_host[f];
+      require(P.num_trees >= 1 && P.num_trees <= AIWC_RF_MAX_TREES, "num_trees must be in [1, 2^14]");
+      require(P.mtry >= 1 && P.mtry <= n_cols, "mtry must be in [1, n_cols]");
+      require(P.min_node_size >= 1, "min_node_size must be >= 1");
+      require(P.bootstrap == 0 || P.bootstrap == 1, "bootstrap must be 0 or 1");
+      const int32_t h = heldout_fold_host ? heldout_fold_host[f] : -1;
+      require(h >= -1 && h <= 127, "heldout fold must be in [-1, 127]");
+      need_folds |= h >= 0;
+      total_trees += P.num_trees;
+      mtry_max = std::max(mtry_max, P.mtry);
+    }
+    require(!need_folds || fold_id != nullptr, "fold_id is NULL but a forest holds out a fold");
+    require(total_trees <= (int64_t)INT32_MAX, "too many trees in one call");
+
+    // training-row lists, one per distinct held-out fold
+    std::vector<int32_t> train_rows;
+    std::map<int32_t, std::pair<int64_t, int32_t>> lists;  // fold -> (offset, n_train)
+    lists[-1] = {-1, (int32_t)n};
+    if (need_folds) {
+      std::vector<int8_t> folds((size_t)n);
+      AIWC_HIP(hipMemcpyAsync(folds.data(), fold_id, (size_t)n, hipMemcpyDeviceToHost, s));
+      AIWC_HIP(hipStreamSynchronize(s));
+      std::set<int32_t> wanted;
+      for (int32_t f = 0; f < n_forests; ++f)
+        if (heldout_fold_host[f] >= 0) wanted.insert(heldout_fold_host[f]);
+      for (int32_t h : wanted) {
+        const int64_t off = (int64_t)train_rows.size();
+        for (int64_t i = 0; i < n; ++i)
+          if (folds[i] != h) train_rows.push_back((int32_t)i);
+        const int64_t cnt = (int64_t)train_rows.size() - off;
+        require(cnt >= 1, "a held-out fold leaves no training rows");
+        lists[h] = {off, (int32_t)cnt};
+      }
+    }
+
+    std::unique_ptr<aiwc_rf_forest> F(new aiwc_rf_forest());
+    AIWC_HIP(hipGetDevice(&F->device));
+    F->n_cols = n_cols;
+    F->params.assign(params_host, params_host + n_forests);
+    F->tasks.reserve((size_t)total_trees);
+    int64_t pool = 0, n_cap = 1;
+    for (int32_t f = 0; f < n_forests; ++f) {
+      const aiwc_rf_params& P = params_host[f];
+      const auto& L = lists[heldout_fold_host ? heldout_fold_host[f] : -1];
+      F->first_task.push_back((int64_t)F->tasks.size());
+      const int64_t cap = 2 * (int64_t)L.second - 1;
+      n_cap = std::max<int64_t>(n_cap, L.second);
+      for (int32_t t = 0; t < P.num_trees; ++t) {
+        TreeTask T;
+        T.forest = f;
+        T.tree = t;
+        T.n_train = L.second;
+        T.mtry = P.mtry;
+        T.min_node = P.min_node_size;
+        T.bootstrap = P.bootstrap;
+        T.seed = P.seed;
+        T.train_off = L.first;
+        T.node_base = pool;
+        T.capacity = cap;
+        pool += cap;
+        F->tasks.push_back(T);
+      }
+    }
+    F->pool_nodes = pool;
+    const int64_t n_tasks = (int64_t)F->tasks.size();
+
+    F->d_tasks.reset((size_t)n_tasks, s);
+    F->nodes.reset((size_t)pool, s);
+    F->node_N.reset((size_t)pool, s);
+    F->n_nodes.reset((size_t)n_tasks, s);
+    F->node_base.reset((size_t)n_tasks, s);
+    F->status.reset(1, s);
+    AIWC_HIP(hipHostMalloc((void**)&F->status_host, sizeof(uint32_t), hipHostMallocDefault));
+    *F->status_host = 0;
+    AIWC_HIP(hipEventCreateWithFlags(&F->done, hipEventDisableTiming));
+    {
+      std::vector<int64_t> bases((size_t)n_tasks);
+      for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
+      AIWC_HIP(hipMemcpyAsync(F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * n_tasks, hipMemcpyHostToDevice, s));
+      AIWC_HIP(hipMemcpyAsync(F->node_base.p, bases.data(), sizeof(int64_t) * n_tasks, hipMemcpyHostToDevice, s));
+      // the staging copies above read pageable host memory; wait before it goes out of scope
+      AIWC_HIP(hipStreamSynchronize(s));
+    }
+    DevBuf<int32_t> d_train(train_rows.size(), s);
+    if (!train_rows.empty())
+      AIWC_HIP(hipMemcpyAsync(d_train.p, train_rows.data(), sizeof(int32_t) * train_rows.size(), hipMemcpyHostToDevice, s));
+    DevBuf<int64_t> y_fp((size_t)n, s);
+    DevBuf<uint32_t> queue(1, s);
+
+    const GrowConfig cfg = grow_config(n_cap);
+    const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
+    const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
+
+    if (plain) {
+      // one launch sequence per forest, as separate fits would issue them
+      const int grid_max = grow_grid_size(cfg, n_tasks);
+      DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
+      launch_init(F->status.p, nullptr, s);
+      for (int32_t f = 0; f < n_forests; ++f) {
+        const int64_t t0 = F->first_task[f];
+        const int32_t nt = params_host[f].num_trees;
+        const int grid = grow_grid_size(cfg, nt);
+        launch_init(nullptr, queue.p, s);
+        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
+        launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
+                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid,
+                    s);
+      }
+    } else {
+      const int grid = grow_grid_size(cfg, n_tasks);
+      DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
+      if (n_forests > 1) {
+        // fused grid: the whole fit as one captured graph
+        hipStream_t cs;
+        AIWC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipEvent_t ev;
+        AIWC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        AIWC_HIP(hipEventRecord(ev, s));
+        AIWC_HIP(hipStreamWaitEvent(cs, ev, 0));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        AIWC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+          launch_init(F->status.p, queue.p, cs);
+          launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, cs);
+          launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+                      F->nodes.p, F->node_N.p, F->n_nodes.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid,
+                      cs);
+        } catch (...) {
+          (void)hipStreamEndCapture(cs, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          (void)hipStreamDestroy(cs);
+          (void)hipEventDestroy(ev);
+          throw;
+        }
+        AIWC_HIP(hipStreamEndCapture(cs, &graph));
+        AIWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        AIWC_HIP(hipGraphLaunch(exec, s));
+        AIWC_HIP(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        (void)hipEventDestroy(ev);
+      } else {
+        launch_init(F->status.p, queue.p, s);
+        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
+        launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+                    F->nodes.p, F->node_N.p, F->n_nodes.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid, s);
+      }
+    }
+    AIWC_HIP(hipMemcpyAsync(F->status_host, F->status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    AIWC_HIP(hipEventRecord(F->done, s));
+    if (!(flags & AIWC_RF_FIT_ASYNC)) {
+      std::string msg;
+      const int32_t code = resolve_status(F.get(), msg);
+      if (code != AIWC_RF_OK) fail(code, msg);
+    }
+    *forest = F.release();
+  });
+}
+
+int aiwc_rf_forest_wait(const aiwc_rf_forest* f) {
+  int32_t code = AIWC_RF_OK;
+  std::string msg;
+  const int rc = guard([&] {
+    require(f != nullptr, "forest is NULL");
+    code = resolve_status(f, msg);
+  });
+  if (rc != AIWC_RF_OK) return rc;
+  if (code != AIWC_RF_OK) g_last_error = msg;
+  return code;
+}
+
+int aiwc_rf_forest_info(const aiwc_rf_forest* f, int32_t forest_index, int32_t* n_forests_host, int32_t* n_cols_host,
+                        int32_t* num_trees_host, int64_t* total_nodes_host) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    if (n_forests_host) *n_forests_host = (int32_t)f->params.size();
+    if (n_cols_host) *n_cols_host = f->n_cols;
+    if (num_trees_host) *num_trees_host = f->params[forest_index].num_trees;
+    if (total_nodes_host) {
+      std::string msg;
+      const int32_t code = resolve_status(f, msg);
+      if (code != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "fit failed: " + msg);
+      const int32_t nt = f->params[forest_index].num_trees;
+      std::vector<int32_t> nn((size_t)nt);
+      AIWC_HIP(hipMemcpy(nn.data(), f->n_nodes.p + f->first_task[forest_index], sizeof(int32_t) * nt,
+                         hipMemcpyDeviceToHost));
+      int64_t tot = 0;
+      for (int32_t v : nn) tot += v;
+      *total_nodes_host = tot;
+    }
+  });
+}
+
+int aiwc_rf_forest_tree_sizes(const aiwc_rf_forest* f, int32_t forest_index, int32_t tree_begin, int32_t tree_end,
+                              int64_t* n_nodes_host) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    require(n_nodes_host != nullptr, "null pointer argument");
+    const int32_t nt = f->params[forest_index].num_trees;
+    require(tree_begin >= 0 && tree_begin < tree_end && tree_end <= nt, "tree range out of bounds");
+    std::string msg;
+    const int32_t code = resolve_status(f, msg);
+    if (code != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "fit failed: " + msg);
+    std::vector<int32_t> nn((size_t)(tree_end - tree_begin));
+    AIWC_HIP(hipMemcpy(nn.data(), f->n_nodes.p + f->first_task[forest_index] + tree_begin,
+                       sizeof(int32_t) * nn.size(), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < nn.size(); ++i) n_nodes_host[i] = nn[i];
+  });
+}
+
+int aiwc_rf_forest_export_host(const aiwc_rf_forest* f, int32_t forest_index, int32_t tree_begin, int32_t tree_end,
+                               uint8_t* col_host, uint8_t* bin_host, int32_t* left_host, int64_t* q_host,
+                               int32_t* N_host) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    const int32_t nt = f->params[forest_index].num_trees;
+    require(tree_begin >= 0 && tree_begin < tree_end && tree_end <= nt, "tree range out of bounds");
+    std::string msg;
+    const int32_t code = resolve_status(f, msg);
+    if (code != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "fit failed: " + msg);
+    const int64_t t0 = f->first_task[forest_index];
+    std::vector<int32_t> nn((size_t)(tree_end - tree_begin));
+    AIWC_HIP(hipMemcpy(nn.data(), f->n_nodes.p + t0 + tree_begin, sizeof(int32_t) * nn.size(), hipMemcpyDeviceToHost));
+    size_t out = 0;
+    std::vector<uint64_t> words;
+    std::vector<uint32_t> N;
+    for (int32_t t = tree_begin; t < tree_end; ++t) {
+      const size_t cnt = (size_t)nn[t - tree_begin];
+      const int64_t base = f->tasks[t0 + t].node_base;
+      words.resize(cnt);
+      N.resize(cnt);
+      AIWC_HIP(hipMemcpy(words.data(), f->nodes.p + base, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost));
+      AIWC_HIP(hipMemcpy(N.data(), f->node_N.p + base, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost));
+      unpack_nodes(words, N, cnt, col_host ? col_host + out : nullptr, bin_host ? bin_host + out : nullptr,
+                   left_host ? left_host + out : nullptr, q_host ? q_host + out : nullptr,
+                   N_host ? N_host + out : nullptr);
+      out += cnt;
+    }
+  });
+}
+
+void aiwc_rf_forest_free(aiwc_rf_forest* f) {
+  if (!f) return;
+  (void)hipDeviceSynchronize();
+  if (f->done) (void)hipEventDestroy(f->done);
+  if (f->status_host) (void)hipHostFree(f->status_host);
+  delete f;
+}
+
+int aiwc_rf_predict(const aiwc_rf_forest* f, int32_t forest_index, const uint8_t* codes, int64_t n, double* y_log10_out,
+                    void* stream) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    require(n >= 0, "n must be >= 0");
+    if (n == 0) return;
+    require(codes && y_log10_out, "null pointer argument");
+    hipStream_t s = as_stream(stream);
+    const int32_t nt = f->params[forest_index].num_trees;
+    const int64_t t0 = f->first_task[forest_index];
+    require_fitted(f);
+    DevBuf<int64_t> sum((size_t)n, s);
+    launch_predict(f->nodes.p, f->node_base.p, (int32_t)t0, (int32_t)(t0 + nt), codes, n, f->n_cols, sum.p,
+                   y_log10_out, nt, s);
+  });
+}
+
+int aiwc_rf_predict_sum(const aiwc_rf_forest* f, int32_t forest_index, int32_t tree_begin, int32_t tree_end,
+                        const uint8_t* codes, int64_t n, int64_t* sum_out, void* stream) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    const int32_t nt = f->params[forest_index].num_trees;
+    require(tree_begin >= 0 && tree_begin < tree_end && tree_end <= nt, "tree range out of bounds");
+    require(n >= 0, "n must be >= 0");
+    if (n == 0) return;
+    require(codes && sum_out, "null pointer argument");
+    hipStream_t s = as_stream(stream);
+    const int64_t t0 = f->first_task[forest_index];
+    require_fitted(f);
+    launch_predict(f->nodes.p, f->node_base.p, (int32_t)(t0 + tree_begin), (int32_t)(t0 + tree_end), codes, n,
+                   f->n_cols, sum_out, nullptr, nt, s);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Host-side internals of libaiwc_rf: error plumbing, the device memory cache,
+// handle layouts and the kernel launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/aiwc_rf.h"
+
+namespace aiwc {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws Error; the C ABI converts it to a return code
+// and a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define AIWC_HIP(call) ::aiwc::hip_check((call), #call)
+
+// ---------------------------------------------------------------------------
+// Device memory cache.  Blocks are rounded up to 1 MiB multiples (small blocks
+// to 256 B) and kept for reuse after release; a block released from one stream
+// and reused on another waits on an event recorded at release time.
+// ---------------------------------------------------------------------------
+void* dev_alloc(size_t bytes, hipStream_t stream);
+void dev_release(void* p, hipStream_t stream);
+void dev_cache_trim();  // hand every cached block back to HIP
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(size_t count, hipStream_t stream) { reset(count, stream); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; s = o.s;
+      o.p = nullptr; o.n = 0;
+    }
+    return *this;
+  }
+  void reset(size_t count, hipStream_t stream) {
+    release();
+    s = stream;
+    n = count;
+    p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), stream)) : nullptr;
+  }
+  void release() {
+    if (p) dev_release(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// Handles.
+// ---------------------------------------------------------------------------
+}  // namespace aiwc
+
+struct aiwc_rf_binner {
+  int device = 0;
+  int32_t p = 0;          // feature columns
+  int32_t n_devices = 0;  // bins of the device column
+  int32_t max_bins = 0;
+  bool has_thresholds = false;
+  std::vector<int32_t> n_bins;     // p + 1
+  std::vector<float> thresholds;   // p * 255
+  aiwc::DevBuf<int32_t> d_n_bins;  // p + 1
+  aiwc::DevBuf<float> d_thresholds;
+};
+
+namespace aiwc {
+
+// One tree to grow: which forest, which Philox tree index, its parameters and
+// where its rows and nodes live.
+struct TreeTask {
+  int32_t forest;
+  int32_t tree;
+  int32_t n_train;
+  int32_t mtry;
+  int32_t min_node;
+  int32_t bootstrap;
+  uint64_t seed;
+  int64_t train_off;  // offset into the training-row lists, -1 = rows 0..n_train-1
+  int64_t node_base;  // first node of the tree's slot in the node pool
+  int64_t capacity;   // node slots reserved for the tree (2 n_train - 1)
+};
+
+// Status bits a fit raises on the device.
+constexpr uint32_t kStatusBadY = 1u;
+constexpr uint32_t kStatusBadCode = 2u;
+constexpr uint32_t kStatusCapacity = 4u;
+constexpr uint32_t kStatusBadFeature = 8u;
+constexpr uint32_t kStatusBadDevice = 16u;
+
+}  // namespace aiwc
+
+struct aiwc_rf_forest {
+  int device = 0;
+  int32_t n_cols = 0;
+  std::vector<aiwc_rf_params> params;      // per forest
+  std::vector<int64_t> first_task;         // per forest, index of tree 0 in the task list
+  std::vector<aiwc::TreeTask> tasks;       // host copy
+  aiwc::DevBuf<aiwc::TreeTask> d_tasks;
+  aiwc::DevBuf<uint64_t> nodes;            // node words, all slots
+  aiwc::DevBuf<uint32_t> node_N;           // bootstrap weight per node
+  aiwc::DevBuf<int32_t> n_nodes;           // per task
+  aiwc::DevBuf<int64_t> node_base;         // per task, device copy for traversal
+  aiwc::DevBuf<uint32_t> status;           // device status word
+  uint32_t* status_host = nullptr;         // pinned
+  hipEvent_t done = nullptr;
+  int32_t fit_status = 0;                  // resolved status after wait
+  bool waited = false;
+  int64_t pool_nodes = 0;
+};
+
+namespace aiwc {
+
+// ---------------------------------------------------------------------------
+// Launchers (implemented in the .hip translation units).
+// ---------------------------------------------------------------------------
+// bin.hip
+void launch_bin_fit(const float* X, const int32_t* dev, int64_t n, int32_t p, int32_t n_devices, int32_t max_bins,
+                    int32_t* d_n_bins, float* d_thresholds, uint32_t* d_status, hipStream_t s);
+void launch_bin_encode(const float* X, const int32_t* dev, int64_t n, int32_t p, int32_t n_devices,
+                       const int32_t* d_n_bins, const float* d_thresholds, uint8_t* codes, uint32_t* d_status,
+                       hipStream_t s);
+
+// fit.hip
+struct GrowConfig {
+  int block = 512;      // threads per workgroup
+  int wg_per_cu = 0;    // 0 = as many as occupancy allows
+};
+void launch_init(uint32_t* d_status, uint32_t* d_queue, hipStream_t s);  // either may be null
+void launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
+void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
+                    int64_t* y_fp, uint32_t* d_status, hipStream_t s);
+size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
+int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks);
+void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
+                 const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
+                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, uint32_t* d_queue, uint32_t* d_status,
+                 uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s);
+
+// predict.hip
+void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
+                    const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,
+                    hipStream_t s);
+
+// Device properties of the current device (cached).
+struct DeviceInfo {
+  int device;
+  int cus;
+  size_t lds_per_block;
+};
+const DeviceInfo& device_info();
+
+}  // namespace aiwc

@@ -1,0 +1,112 @@
+// Batched prediction by tree traversal on gfx950.
+//
+// A thread follows one row down a chunk of trees (left when the row's code in
+// the node's column is <= the node's bin, else right) and adds the leaf values
+// as exact int64.  The grid is (row block x tree chunk); with the chunk index
+// fastest and a multiple of 8 chunks, consecutive workgroups land on different
+// XCDs while each XCD keeps working on the same trees, so the upper levels of
+// those trees stay in that XCD's L2.  Partial sums of different chunks meet in
+// a 64-bit integer atomic add, which is exact in any order.
+#include "device.h"
+#include "internal.h"
+
+namespace aiwc {
+namespace {
+
+constexpr int kPredBlock = 256;
+constexpr int kInterleave = 4;  // trees traversed together per thread to overlap load latency
+
+__global__ __launch_bounds__(kPredBlock) void k_traverse(const uint64_t* __restrict__ nodes,
+                                                         const int64_t* __restrict__ node_base, int32_t tree_begin,
+                                                         int32_t tree_end, int32_t chunk, int32_t n_chunks,
+                                                         const uint8_t* __restrict__ codes, int64_t n, int32_t C,
+                                                         unsigned long long* __restrict__ sum, int accumulate) {
+  const int32_t ci = (int32_t)(blockIdx.x % (unsigned)n_chunks);
+  const int64_t rb = blockIdx.x / (unsigned)n_chunks;
+  const int64_t r = rb * kPredBlock + threadIdx.x;
+  if (r >= n) return;
+  const int32_t t0 = tree_begin + ci * chunk;
+  const int32_t t1 = min(tree_end, t0 + chunk);
+  if (t0 >= t1) return;
+  const uint8_t* rp = codes + r * C;
+  int64_t acc = 0;
+  int32_t t = t0;
+  for (; t + kInterleave <= t1; t += kInterleave) {
+    const uint64_t* tn[kInterleave];
+    uint64_t v[kInterleave];
+#pragma unroll
+    for (int u = 0; u < kInterleave; ++u) {
+      tn[u] = nodes + node_base[t + u];
+      v[u] = tn[u][0];
+    }
+    bool open = true;
+    while (open) {
+      open = false;
+#pragma unroll
+      for (int u = 0; u < kInterleave; ++u) {
+        if (node_col(v[u]) != kLeafCol) {
+          const uint32_t c = node_col(v[u]);
+          const uint32_t next = node_left(v[u]) + (rp[c] > node_bin(v[u]) ? 1u : 0u);
+          v[u] = tn[u][next];
+          open = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kInterleave; ++u) acc += node_q(v[u]);
+  }
+  for (; t < t1; ++t) {
+    const uint64_t* tn = nodes + node_base[t];
+    uint64_t v = tn[0];
+    while (node_col(v) != kLeafCol) v = tn[node_left(v) + (rp[node_col(v)] > node_bin(v) ? 1u : 0u)];
+    acc += node_q(v);
+  }
+  if (accumulate)
+    atomicAdd(&sum[r], (unsigned long long)acc);
+  else
+    sum[r] = (unsigned long long)acc;
+}
+
+__global__ void k_zero_i64(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// yhat = (P * 2^-32) / num.trees: an exact scaling then one rounded division.
+__global__ void k_finalize(const int64_t* sum, int64_t n, double trees, double* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = ((double)sum[i] * 0x1p-32) / trees;
+}
+
+}  // namespace
+
+void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
+                    const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  const int32_t n_trees = tree_end - tree_begin;
+  const int64_t row_blocks = (n + kPredBlock - 1) / kPredBlock;
+  const int64_t target = 4LL * device_info().cus;
+  int64_t n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_trees, (target + row_blocks - 1) / row_blocks));
+  if (n_chunks > 1) n_chunks = std::min<int64_t>(n_trees, (n_chunks + 7) / 8 * 8);
+  const int32_t chunk = (int32_t)((n_trees + n_chunks - 1) / n_chunks);
+  n_chunks = (n_trees + chunk - 1) / chunk;
+  const int accumulate = n_chunks > 1 ? 1 : 0;
+  if (accumulate) {
+    const int zb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    k_zero_i64<<<zb, 256, 0, s>>>(reinterpret_cast<unsigned long long*>(sum), n);
+    AIWC_HIP(hipGetLastError());
+  }
+  const int64_t blocks = row_blocks * n_chunks;
+  k_traverse<<<(unsigned)blocks, kPredBlock, 0, s>>>(nodes, node_base, tree_begin, tree_end, chunk, (int32_t)n_chunks,
+                                                      codes, n, C, reinterpret_cast<unsigned long long*>(sum),
+                                                      accumulate);
+  AIWC_HIP(hipGetLastError());
+  if (y) {
+    const int fb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    k_finalize<<<fb, 256, 0, s>>>(sum, n, (double)num_trees, y);
+    AIWC_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace aiwc

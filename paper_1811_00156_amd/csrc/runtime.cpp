@@ -1,0 +1,140 @@
+// Host runtime of libaiwc_rf: errors, device properties and the device memory
+// cache that every allocation of the library goes through.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace aiwc {
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    fail(AIWC_RF_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  fail(AIWC_RF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const DeviceInfo& device_info() {
+  static std::mutex mu;
+  static std::map<int, DeviceInfo> cache;
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  DeviceInfo d;
+  d.device = dev;
+  AIWC_HIP(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int lds = 0;
+  AIWC_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  d.lds_per_block = (size_t)lds;
+  return cache.emplace(dev, d).first->second;
+}
+
+namespace {
+
+struct Block {
+  void* p;
+  size_t bytes;
+  int device;
+  hipStream_t stream;  // stream of the last release
+  hipEvent_t ready;    // recorded on `stream` at release
+};
+
+struct Cache {
+  std::mutex mu;
+  std::multimap<size_t, Block> free_blocks;  // by rounded size
+  std::unordered_map<void*, Block> live;
+};
+
+Cache& cache() {
+  static Cache* c = new Cache();  // never destroyed: releases may run during exit
+  return *c;
+}
+
+size_t round_size(size_t b) {
+  if (b == 0) return 256;
+  if (b < (1u << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t mib = size_t(1) << 20;
+  return (b + mib - 1) / mib * mib;
+}
+
+void free_all_cached_locked(Cache& c) {
+  for (auto& kv : c.free_blocks) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(kv.second.device);
+    (void)hipEventSynchronize(kv.second.ready);
+    (void)hipEventDestroy(kv.second.ready);
+    (void)hipFree(kv.second.p);
+    (void)hipSetDevice(prev);
+  }
+  c.free_blocks.clear();
+}
+
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t stream) {
+  Cache& c = cache();
+  const size_t r = round_size(bytes);
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(c.mu);
+  for (auto it = c.free_blocks.lower_bound(r); it != c.free_blocks.end() && it->first == r; ++it) {
+    if (it->second.device != dev) continue;
+    Block b = it->second;
+    c.free_blocks.erase(it);
+    if (b.stream != stream) AIWC_HIP(hipStreamWaitEvent(stream, b.ready, 0));
+    c.live.emplace(b.p, b);
+    return b.p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    free_all_cached_locked(c);
+    e = hipMalloc(&p, r);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(AIWC_RF_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed: " + hipGetErrorString(e));
+  }
+  Block b{p, r, dev, stream, nullptr};
+  AIWC_HIP(hipEventCreateWithFlags(&b.ready, hipEventDisableTiming));
+  c.live.emplace(p, b);
+  return p;
+}
+
+void dev_release(void* p, hipStream_t stream) {
+  if (!p) return;
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;
+  Block b = it->second;
+  c.live.erase(it);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != b.device) (void)hipSetDevice(b.device);
+  b.stream = stream;
+  (void)hipEventRecord(b.ready, stream);
+  if (prev != b.device) (void)hipSetDevice(prev);
+  c.free_blocks.emplace(b.bytes, b);
+}
+
+void dev_cache_trim() {
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  free_all_cached_locked(c);
+}
+
+}  // namespace aiwc

@@ -1,0 +1,327 @@
+"""ctypes binding of libaiwc_rf.so (the C ABI in include/aiwc_rf.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.  Device
+arrays are torch tensors on the current HIP device (torch supplies memory and
+streams); the default stream argument is torch's current stream.  The function
+names are those of the C ABI.  Importing this module fails loudly when the
+library has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaiwc_rf.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
+FIT_FUSED, FIT_PLAIN, FIT_ASYNC = 0, 1, 2
+LEAF = 255
+MAX_ROWS = 1 << 18
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_L = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i32, _i64, _u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+
+
+class Params(ctypes.Structure):
+    """aiwc_rf_params: num.trees, mtry, min.node.size (Sec. III-B), bootstrap, seed."""
+
+    _fields_ = [("num_trees", ctypes.c_int32), ("mtry", ctypes.c_int32), ("min_node_size", ctypes.c_int32),
+                ("bootstrap", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_L, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("aiwc_rf_bin", [_P, _P, _i64, _i32, _i32, _i32, _P, _P, _P])
+_sig("aiwc_rf_binner_from_counts", [_P, _i32, _P])
+_sig("aiwc_rf_binner_export_host", [_P, _P, _P, _P, _P])
+_sig("aiwc_rf_binner_free", [_P], None)
+_sig("aiwc_rf_fit", [_P, _i64, _i32, _P, _P, _P, _P, _P, _i32, _u32, _P, _P])
+_sig("aiwc_rf_forest_wait", [_P])
+_sig("aiwc_rf_forest_info", [_P, _i32, _P, _P, _P, _P])
+_sig("aiwc_rf_forest_tree_sizes", [_P, _i32, _i32, _i32, _P])
+_sig("aiwc_rf_forest_export_host", [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P])
+_sig("aiwc_rf_forest_free", [_P], None)
+_sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
+_sig("aiwc_rf_predict_sum", [_P, _i32, _i32, _i32, _P, _i64, _P, _P])
+_sig("aiwc_rf_server_create", [_P, _i32, _i64, _i32, _i32, _P])
+_sig("aiwc_rf_server_submit", [_P, _P, _i64, _P, _P])
+_sig("aiwc_rf_server_poll", [_P, _P, _P, _i32, _P])
+_sig("aiwc_rf_server_drain", [_P])
+_sig("aiwc_rf_server_stats", [_P, _P, _P, _P])
+_sig("aiwc_rf_server_free", [_P], None)
+_sig("aiwc_rf_last_error", [], ctypes.c_char_p)
+
+SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
+           "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_tree_sizes",
+           "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
+           "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
+           "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
+
+
+class RFError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        msg = _L.aiwc_rf_last_error().decode()
+        super().__init__(f"{what} failed ({rc}): {msg}")
+        self.rc = rc
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise RFError(rc, what)
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, what):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Binner:
+    """Handle of a fitted binning (thresholds per feature column + bin counts)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+
+    def export(self):
+        p, d = ctypes.c_int32(), ctypes.c_int32()
+        _check(_L.aiwc_rf_binner_export_host(self.handle, ctypes.byref(p), ctypes.byref(d), None, None),
+               "aiwc_rf_binner_export_host")
+        nb = np.zeros(p.value + 1, np.int32)
+        thr = np.zeros((p.value, 255), np.float32)
+        rc = _L.aiwc_rf_binner_export_host(self.handle, None, None, _host(nb), _host(thr))
+        if rc != OK:  # counts-only binner
+            _check(_L.aiwc_rf_binner_export_host(self.handle, None, None, _host(nb), None),
+                   "aiwc_rf_binner_export_host")
+            thr = None
+        return nb, thr
+
+    @property
+    def n_bins(self) -> np.ndarray:
+        return self.export()[0]
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _L.aiwc_rf_binner_free(self.handle)
+            self.handle = None
+
+
+def aiwc_rf_bin(X, device_id, n_devices: int, max_bins: int = 256, binner: Binner | None = None, codes=None,
+                stream=None):
+    """Bin features X (n x p float32) and device ids (n int32) to codes (n x (p+1) uint8).
+
+    Fits a new binner unless one is given.  Returns (codes, binner)."""
+    import torch
+
+    n, p = X.shape
+    if codes is None:
+        codes = torch.empty((n, p + 1), dtype=torch.uint8, device=X.device)
+    h = ctypes.c_void_p(binner.handle.value if binner is not None else None)
+    _check(_L.aiwc_rf_bin(_dev(X, torch.float32, "X"), _dev(device_id, torch.int32, "device_id"), n, p, n_devices,
+                          max_bins, ctypes.byref(h), _dev(codes, torch.uint8, "codes"), _stream(stream)),
+           "aiwc_rf_bin")
+    return codes, (binner if binner is not None else Binner(h))
+
+
+def aiwc_rf_binner_from_counts(n_bins) -> Binner:
+    nb = np.ascontiguousarray(n_bins, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(_L.aiwc_rf_binner_from_counts(_host(nb), nb.shape[0], ctypes.byref(h)), "aiwc_rf_binner_from_counts")
+    return Binner(h)
+
+
+class Forest:
+    """Handle of one or many fitted forests (device resident)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n_forests: int):
+        self.handle = handle
+        self.n_forests = n_forests
+
+    def wait(self) -> int:
+        return _L.aiwc_rf_forest_wait(self.handle)
+
+    def num_trees(self, forest_index: int = 0) -> int:
+        nt = ctypes.c_int32()
+        _check(_L.aiwc_rf_forest_info(self.handle, forest_index, None, None, ctypes.byref(nt), None),
+               "aiwc_rf_forest_info")
+        return nt.value
+
+    def total_nodes(self, forest_index: int = 0) -> int:
+        tot = ctypes.c_int64()
+        _check(_L.aiwc_rf_forest_info(self.handle, forest_index, None, None, None, ctypes.byref(tot)),
+               "aiwc_rf_forest_info")
+        return tot.value
+
+    def tree_sizes(self, forest_index: int = 0, tree_begin: int = 0, tree_end: int | None = None) -> np.ndarray:
+        if tree_end is None:
+            tree_end = self.num_trees(forest_index)
+        out = np.zeros(tree_end - tree_begin, np.int64)
+        _check(_L.aiwc_rf_forest_tree_sizes(self.handle, forest_index, tree_begin, tree_end, _host(out)),
+               "aiwc_rf_forest_tree_sizes")
+        return out
+
+    def export(self, forest_index: int = 0, tree_begin: int = 0, tree_end: int | None = None) -> list[dict]:
+        """Node arrays (col, bin, left, q, N) of each tree in [tree_begin, tree_end)."""
+        if tree_end is None:
+            tree_end = self.num_trees(forest_index)
+        sizes = self.tree_sizes(forest_index, tree_begin, tree_end)
+        tot = int(sizes.sum())
+        col = np.zeros(tot, np.uint8)
+        bn = np.zeros(tot, np.uint8)
+        left = np.zeros(tot, np.int32)
+        q = np.zeros(tot, np.int64)
+        N = np.zeros(tot, np.int32)
+        _check(_L.aiwc_rf_forest_export_host(self.handle, forest_index, tree_begin, tree_end, _host(col), _host(bn),
+                                             _host(left), _host(q), _host(N)), "aiwc_rf_forest_export_host")
+        out, s = [], 0
+        for k in sizes:
+            k = int(k)
+            out.append({"col": col[s:s + k], "bin": bn[s:s + k], "left": left[s:s + k], "q": q[s:s + k],
+                        "N": N[s:s + k]})
+            s += k
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _L.aiwc_rf_forest_free(self.handle)
+            self.handle = None
+
+
+def make_params(num_trees: int, mtry: int, min_node_size: int, bootstrap: bool = True, seed: int = 1) -> Params:
+    return Params(num_trees, mtry, min_node_size, 1 if bootstrap else 0, seed)
+
+
+def aiwc_rf_fit(codes, binner: Binner, y_log10, params, fold_id=None, heldout_fold=None, flags: int = FIT_FUSED,
+                stream=None) -> Forest:
+    """Fit one forest (params: a Params) or a grid (params: a sequence of Params, with
+    heldout_fold giving each forest's held-out fold id or -1)."""
+    import torch
+
+    n, C = codes.shape
+    plist = [params] if isinstance(params, Params) else list(params)
+    arr = (Params * len(plist))(*plist)
+    hf = None
+    if heldout_fold is not None:
+        hf = np.ascontiguousarray(heldout_fold, dtype=np.int32)
+        assert hf.shape[0] == len(plist)
+    fp = _dev(fold_id, torch.int8, "fold_id") if fold_id is not None else None
+    h = ctypes.c_void_p()
+    _check(_L.aiwc_rf_fit(_dev(codes, torch.uint8, "codes"), n, C, binner.handle, _dev(y_log10, torch.float64, "y"),
+                          fp, arr, None if hf is None else _host(hf), len(plist), flags, ctypes.byref(h),
+                          _stream(stream)), "aiwc_rf_fit")
+    return Forest(h, len(plist))
+
+
+def aiwc_rf_predict(forest: Forest, codes, forest_index: int = 0, out=None, stream=None):
+    """Predicted log10 execution time of each row of codes (float64 device tensor)."""
+    import torch
+
+    n = codes.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=codes.device)
+    _check(_L.aiwc_rf_predict(forest.handle, forest_index, _dev(codes, torch.uint8, "codes"), n,
+                              _dev(out, torch.float64, "out"), _stream(stream)), "aiwc_rf_predict")
+    return out
+
+
+def aiwc_rf_predict_sum(forest: Forest, codes, tree_begin: int, tree_end: int, forest_index: int = 0, out=None,
+                        stream=None):
+    """Exact int64 sums of leaf values over trees [tree_begin, tree_end)."""
+    import torch
+
+    n = codes.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=codes.device)
+    _check(_L.aiwc_rf_predict_sum(forest.handle, forest_index, tree_begin, tree_end,
+                                  _dev(codes, torch.uint8, "codes"), n, _dev(out, torch.int64, "out"),
+                                  _stream(stream)), "aiwc_rf_predict_sum")
+    return out
+
+
+@dataclass
+class ServerStats:
+    rows: int
+    batches: int
+    peak_bytes: int
+
+
+class Server:
+    """aiwc_rf_server_*: continuous-batching prediction server over a resident forest."""
+
+    def __init__(self, forest: Forest, forest_index: int = 0, memory_budget_bytes: int = 1 << 28,
+                 max_batch_rows: int = 1 << 16, n_streams: int = 4):
+        self.forest = forest  # keeps the forest alive
+        self.handle = ctypes.c_void_p()
+        _check(_L.aiwc_rf_server_create(forest.handle, forest_index, memory_budget_bytes, max_batch_rows, n_streams,
+                                        ctypes.byref(self.handle)), "aiwc_rf_server_create")
+        self._keep = {}
+
+    def submit(self, codes: np.ndarray, out: np.ndarray) -> int:
+        """Queue rows (uint8 n x C host array); results land in out (float64[n])."""
+        assert codes.dtype == np.uint8 and codes.flags.c_contiguous
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.shape[0] == codes.shape[0]
+        t = ctypes.c_int64()
+        _check(_L.aiwc_rf_server_submit(self.handle, _host(codes), codes.shape[0], _host(out), ctypes.byref(t)),
+               "aiwc_rf_server_submit")
+        self._keep[t.value] = (codes, out)
+        return t.value
+
+    def poll(self, max_tickets: int = 4096):
+        tk = np.zeros(max_tickets, np.int64)
+        lat = np.zeros(max_tickets, np.float64)
+        nd = ctypes.c_int32()
+        _check(_L.aiwc_rf_server_poll(self.handle, _host(tk), _host(lat), max_tickets, ctypes.byref(nd)),
+               "aiwc_rf_server_poll")
+        k = nd.value
+        for t in tk[:k]:
+            self._keep.pop(int(t), None)
+        return tk[:k].copy(), lat[:k].copy()
+
+    def drain(self):
+        _check(_L.aiwc_rf_server_drain(self.handle), "aiwc_rf_server_drain")
+
+    def stats(self) -> ServerStats:
+        r, b, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_L.aiwc_rf_server_stats(self.handle, ctypes.byref(r), ctypes.byref(b), ctypes.byref(p)),
+               "aiwc_rf_server_stats")
+        return ServerStats(r.value, b.value, p.value)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _L.aiwc_rf_server_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,62 @@
+"""The C-ABI library loads on the CPU and exports every declared entry point.
+
+No compute call is made here (there is no GPU); only argument checks that fail
+before any HIP call are exercised.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aiwc_rf.h")
+LIB = os.path.join(ROOT, "paper_1811_00156_amd", "libaiwc_rf.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aiwc_rf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1811_00156_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), f"{name} is declared in aiwc_rf.h but not exported"
+
+
+def test_binding_covers_the_header():
+    from paper_1811_00156_amd import rf
+
+    assert sorted(rf.SYMBOLS) == declared()
+
+
+def test_argument_checks_without_gpu(lib):
+    lib.aiwc_rf_bin.restype = ctypes.c_int
+    lib.aiwc_rf_last_error.restype = ctypes.c_char_p
+    P = ctypes.c_void_p
+    lib.aiwc_rf_bin.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    assert lib.aiwc_rf_bin(None, None, 10, 3, 1, 8, None, None, None) == -1
+    assert b"null" in lib.aiwc_rf_last_error()
+    buf = ctypes.create_string_buffer(64)
+    h = ctypes.c_void_p()
+    assert lib.aiwc_rf_bin(buf, buf, 0, 3, 1, 8, ctypes.byref(h), buf, None) == -1
+    assert lib.aiwc_rf_bin(buf, buf, 10, 256, 1, 8, ctypes.byref(h), buf, None) == -1
+    assert lib.aiwc_rf_bin(buf, buf, 10, 3, 0, 8, ctypes.byref(h), buf, None) == -1
+    assert lib.aiwc_rf_bin(buf, buf, 10, 3, 1, 1, ctypes.byref(h), buf, None) == -1
+    lib.aiwc_rf_binner_from_counts.argtypes = [P, ctypes.c_int32, P]
+    counts = (ctypes.c_int32 * 3)(4, 0, 2)
+    assert lib.aiwc_rf_binner_from_counts(counts, 3, ctypes.byref(h)) == -1
+    lib.aiwc_rf_server_submit.argtypes = [P, P, ctypes.c_int64, P, P]
+    assert lib.aiwc_rf_server_submit(None, None, 1, None, None) == -1
