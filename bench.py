@@ -1,0 +1,336 @@
+"""Benchmark of the random-forest performance model on one MI355X.
+
+python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+
+One step is one pass of the whole hot path over one batch of synthetic input
+that is already resident in device memory: quantile binning of the feature
+matrix, the forest fit (fixed-point response, bootstrap, per-node mtry draw,
+histogram and split search, partition, leaves) and the prediction of every row.
+
+Workloads (synthetic, shaped like the paper's frame: 37 kernels x 4 sizes x 15
+devices, 34 features; see paper_1811_00156_amd/synth.py):
+  c1  2220 rows, 64 bins, 100 trees, mtry 6, min.node.size 5
+  c2  2220 rows, 256 bins, 2000 trees, mtry 12, min.node.size 1   (default)
+  c3  200000 rows x 64 features + 32 devices, 256 bins, 500 trees, mtry 16, min.node.size 5
+  c4  2220 rows, 64 bins, 10 folds x mtry 1..34 x min.node.size {1,3,5,7,9} = 1700 forests x 256 trees,
+      fused single launch vs one launch sequence per forest
+  c5  serving: the c3 forest answers Poisson request streams of 1..4096 rows
+
+Prints ONE JSON line.  `value` is whole-step throughput in rows x trees per
+second (c5: rows per second).  `roofline` describes the tree-growing kernel:
+algorithmic bytes per launch over its event-timed duration.  `cpu_baseline` is
+the CPU oracle timed on the host cores on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    "c1": dict(data="d1", bins=64, num_trees=100, mtry=6, min_node=5),
+    "c2": dict(data="d1", bins=256, num_trees=2000, mtry=12, min_node=1),
+    "c3": dict(data="d3", bins=256, num_trees=500, mtry=16, min_node=5),
+    "c4": dict(data="d1", bins=64, num_trees=256),
+    "c5": dict(data="d3", bins=256, num_trees=500, mtry=16, min_node=5),
+}
+
+METRIC = "forest fit rows·trees/s (fused grid vs plain); predict rows/s + p99 latency"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def grow_bytes(work, mtry, total_nodes):
+    """Algorithmic bytes of the tree-growing kernel.
+
+    Every node whose split is searched reads, for each of its in-bag rows, the
+    8-byte row entry (row, weight, fixed-point response) and the row's code in
+    each of its mtry candidate columns; every node that splits reads each entry
+    and its code in the split column and writes the entry to a child (8 + 1 + 8);
+    every node writes its 8-byte node word and 4-byte weight."""
+    searched_rows, _, part_rows, _ = (int(x) for x in work)
+    return searched_rows * (8 + mtry) + part_rows * 17 + total_nodes * 12
+
+
+def run_cpu_baseline(wl, ds, sample_trees, steps_cap_s=30.0):
+    from oracle import oracle as O
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    b = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
+    t_bin = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    f = O.fit(b.codes, b.n_bins, ds.y, wl["num_trees"], wl["mtry"], wl["min_node"], seed=1,
+              trees=range(sample_trees), n_threads=cores)
+    t_fit = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.predict(f, b.codes)
+    t_pred = time.perf_counter() - t0
+    # scale the sampled trees to the whole forest: fit and predict are linear in trees
+    scale = wl["num_trees"] / sample_trees
+    step_s = t_bin + (t_fit + t_pred) * scale
+    return {"value": ds.n * wl["num_trees"] / step_s, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+            "sample": f"bin all {ds.n} rows + fit and predict {sample_trees} of {wl['num_trees']} trees "
+                      f"(scaled x{scale:g}); measured {t_bin + t_fit + t_pred:.1f} s"}
+
+
+def bench_forest(args, wl_name):
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    wl = WORKLOADS[wl_name]
+    ds = synth.d1() if wl["data"] == "d1" else synth.d3()
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(ds.X).to(dev)
+    did = torch.from_numpy(ds.device).to(dev)
+    y = torch.from_numpy(ds.y).to(dev)
+    prm = rf.make_params(wl["num_trees"], wl["mtry"], wl["min_node"], True, 1)
+    out = torch.empty(ds.n, dtype=torch.float64, device=dev)
+
+    def step():
+        codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm)
+        rf.aiwc_rf_predict(forest, codes, out=out)
+        return forest, binner
+
+    for i in range(args.warmup):
+        log(f"{wl_name} warmup {i}")
+        keep = step()
+    torch.cuda.synchronize()
+    keep = None
+    grow_ms, bin_ms, fit_ms, pred_ms = [], [], [], []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    forests = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[0].record()
+        codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
+        ev[1].record()
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm)
+        ev[2].record()
+        rf.aiwc_rf_predict(forest, codes, out=out)
+        ev[3].record()
+        ev[3].synchronize()
+        bin_ms.append(ev[0].elapsed_time(ev[1]))
+        fit_ms.append(ev[1].elapsed_time(ev[2]))
+        pred_ms.append(ev[2].elapsed_time(ev[3]))
+        grow_ms.append(forest.stats()[1])
+        if forests:
+            forests.pop()  # release the previous step's forest
+        forests.append((forest, binner))
+        log(f"{wl_name} step {i}: bin {bin_ms[-1]:.2f} ms fit {fit_ms[-1]:.2f} ms (grow {grow_ms[-1]:.2f}) "
+            f"predict {pred_ms[-1]:.3f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    forest = forests[-1][0]
+    work, _ = forest.stats()
+    total_nodes = forest.total_nodes()
+    gbytes = grow_bytes(work, wl["mtry"], total_nodes)
+    g_ms = float(np.mean(grow_ms))
+    achieved = gbytes / (g_ms / 1000.0) / 1e9
+    rows_trees = ds.n * wl["num_trees"]
+    res = {
+        "metric": METRIC, "value": rows_trees / (ms_step / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": f"{wl_name}: {ds.n} rows x {ds.p} features + device ({ds.n_devices} levels), "
+                               f"{wl['bins']} bins, num.trees {wl['num_trees']}, mtry {wl['mtry']}, "
+                               f"min.node.size {wl['min_node']}; bin + fit + predict all rows",
+                   "rows": ds.n, "num_trees": wl["num_trees"], "bins": wl["bins"], "mtry": wl["mtry"],
+                   "min_node_size": wl["min_node"]},
+        "breakdown_ms": {"bin": float(np.median(bin_ms)), "fit": float(np.median(fit_ms)),
+                         "grow_kernel": float(np.median(grow_ms)), "predict": float(np.median(pred_ms))},
+        "fit_rows_trees_per_s": rows_trees / (float(np.median(fit_ms)) / 1000.0),
+        "predict_rows_per_s": ds.n / (float(np.median(pred_ms)) / 1000.0),
+        "tree_stats": {"total_nodes": int(total_nodes), "searched_rows": int(work[0]), "searched_nodes": int(work[1]),
+                       "partitioned_rows": int(work[2]), "max_levels": int(work[3])},
+        "roofline": {"kernel": "k_grow", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": int(gbytes), "avg_launch_ms": g_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        sample = {"c1": 100, "c2": 2000, "c3": 16}.get(wl_name, 16)
+        res["cpu_baseline"] = run_cpu_baseline(wl, ds, sample)
+    forests.clear()
+    return res
+
+
+def bench_grid(args):
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    ds = synth.d1()
+    dev = torch.device("cuda:0")
+    folds = synth.cv_folds()
+    combos = synth.grid_forests()
+    params = [rf.make_params(256, m, mn, True, 1) for _, m, mn in combos]
+    held = [f for f, _, _ in combos]
+    X = torch.from_numpy(ds.X).to(dev)
+    did = torch.from_numpy(ds.device).to(dev)
+    y = torch.from_numpy(ds.y).to(dev)
+    fd = torch.from_numpy(folds).to(dev)
+    codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, 64)
+    n_train = np.array([ds.n - int((folds == f).sum()) for f in held])
+    rows_trees = int(n_train.sum()) * 256
+
+    def run(flags):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = rf.aiwc_rf_fit(codes, binner, y, params, fold_id=fd, heldout_fold=held, flags=flags)
+        torch.cuda.synchronize()
+        return g, (time.perf_counter() - t0) * 1000.0
+
+    for i in range(args.warmup):
+        log(f"grid warmup {i}")
+        g, _ = run(rf.FIT_FUSED)
+        del g
+    fused_ms, plain_ms, grow_ms = [], [], []
+    for i in range(args.steps):
+        g, ms = run(rf.FIT_FUSED)
+        fused_ms.append(ms)
+        grow_ms.append(g.stats(0)[1])
+        log(f"grid fused step {i}: {ms:.1f} ms (grow {grow_ms[-1]:.1f} ms)")
+        del g
+        g, ms = run(rf.FIT_PLAIN)
+        plain_ms.append(ms)
+        log(f"grid plain step {i}: {ms:.1f} ms")
+        del g
+    f_ms, p_ms = float(np.median(fused_ms)), float(np.median(plain_ms))
+    res = {
+        "metric": METRIC, "value": rows_trees / (f_ms / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": "c4: 2220 rows, 64 bins, 10 CV folds x mtry 1..34 x min.node.size {1,3,5,7,9} "
+                               "= 1700 forests x 256 trees, one fused launch", "forests": len(params)},
+        "plain_ms": p_ms, "plain_rows_trees_per_s": rows_trees / (p_ms / 1000.0), "fused_speedup": p_ms / f_ms,
+        "grow_kernel_ms": float(np.median(grow_ms)),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        ob = O.bin(ds.X, ds.device, ds.n_devices, 64)
+        rng = np.random.default_rng(0)
+        pick = rng.choice(len(combos), size=6, replace=False)
+        t0 = time.perf_counter()
+        rt = 0
+        for k in pick:
+            f, m, mn = combos[k]
+            train = np.nonzero(folds != f)[0]
+            O.fit(ob.codes, ob.n_bins, ds.y, 256, m, mn, seed=1, train_rows=train, n_threads=cores)
+            rt += train.shape[0] * 256
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+                               "sample": f"6 random forests of the grid (256 trees each), {el:.1f} s"}
+    return res
+
+
+def bench_serve(args):
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    wl = WORKLOADS["c5"]
+    ds = synth.d3()
+    dev = torch.device("cuda:0")
+    codes, binner = rf.aiwc_rf_bin(torch.from_numpy(ds.X).to(dev), torch.from_numpy(ds.device).to(dev),
+                                   ds.n_devices, wl["bins"])
+    forest = rf.aiwc_rf_fit(codes, binner, torch.from_numpy(ds.y).to(dev),
+                            rf.make_params(wl["num_trees"], wl["mtry"], wl["min_node"], True, 1))
+    host_codes = codes.cpu().numpy()
+    n_req = args.requests
+
+    def stream(qps, seed_shift=0):
+        arrivals, sizes, row_seed = synth.request_stream(n_req, qps)
+        rng = np.random.default_rng(row_seed + seed_shift)
+        reqs = [np.ascontiguousarray(host_codes[rng.integers(0, ds.n, size=int(s))]) for s in sizes]
+        return arrivals, reqs
+
+    def serve(arrivals, reqs, open_loop=True):
+        srv = rf.Server(forest, memory_budget_bytes=1 << 26, max_batch_rows=16384, n_streams=4)
+        outs = [np.empty(r.shape[0]) for r in reqs]
+        t0 = time.perf_counter()
+        for a, r, o in zip(arrivals, reqs, outs):
+            if open_loop:
+                while time.perf_counter() - t0 < a:
+                    pass
+            srv.submit(r, o)
+        srv.drain()
+        el = time.perf_counter() - t0
+        _, lat = srv.poll(len(reqs) + 1)
+        st = srv.stats()
+        srv.close()
+        rows = sum(r.shape[0] for r in reqs)
+        return {"rows_per_s": rows / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "batches": st.batches, "requests": len(reqs)}
+
+    arr, reqs = stream(1000.0)
+    log("serve warmup")
+    serve(arr, reqs[:200], open_loop=False)
+    log("serve saturated")
+    sat = serve(arr, reqs, open_loop=False)
+    mean_rows = np.mean([r.shape[0] for r in reqs])
+    points = {}
+    for frac in (0.25, 0.5, 0.8):
+        qps = frac * sat["rows_per_s"] / mean_rows
+        a, r = stream(qps, 1)
+        log(f"serve {frac:.0%} load ({qps:.0f} QPS)")
+        points[f"{int(frac * 100)}%"] = dict(qps=qps, **serve(a, r))
+    a, r = stream(2000.0, 2)
+    log("serve 2000 QPS")
+    points["2000qps"] = dict(qps=2000.0, **serve(a, r))
+    return {
+        "metric": METRIC, "value": sat["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64",
+        "data": "synthetic",
+        "config": {"workload": "c5: serving the c3 forest (500 trees, 65 columns); Poisson arrivals, "
+                               "1..4096 rows per request (log-uniform)", "requests": n_req},
+        "saturated": sat, "load_points": points,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--requests", type=int, default=4000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(trees shard across GPUs by design, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    if args.workload == "c4":
+        res = bench_grid(args)
+    elif args.workload == "c5":
+        res = bench_serve(args)
+    else:
+        res = bench_forest(args, args.workload)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,15 @@ int aiwc_rf_forest_wait(const aiwc_rf_forest* forest);
 int aiwc_rf_forest_info(const aiwc_rf_forest* forest, int32_t forest_index, int32_t* n_forests_host,
                         int32_t* n_cols_host, int32_t* num_trees_host, int64_t* total_nodes_host);
 
+/* Work statistics of a fit, for throughput accounting.  work_host[4] receives,
+ * summed over the trees of forest forest_index: the in-bag rows of every node whose
+ * split was searched, the number of such nodes, the in-bag rows of every node that
+ * split (rows moved to children), and (max over trees) the number of levels grown.
+ * grow_ms_host receives the device time of the call's tree-growing launch(es),
+ * from events recorded on the fit stream around them (for a grid: the whole call).
+ * Either output may be NULL.  Waits for an ASYNC fit. */
+int aiwc_rf_forest_stats(const aiwc_rf_forest* forest, int32_t forest_index, int64_t* work_host, float* grow_ms_host);
+
 /* Node counts of trees [tree_begin, tree_end) of a forest (n_nodes_host[tree_end - tree_begin]). */
 int aiwc_rf_forest_tree_sizes(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
                               int32_t tree_end, int64_t* n_nodes_host);

@@ -291,11 +291,14 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     F->nodes.reset((size_t)pool, s);
     F->node_N.reset((size_t)pool, s);
     F->n_nodes.reset((size_t)n_tasks, s);
+    F->work.reset((size_t)n_tasks * 4, s);
     F->node_base.reset((size_t)n_tasks, s);
     F->status.reset(1, s);
     AIWC_HIP(hipHostMalloc((void**)&F->status_host, sizeof(uint32_t), hipHostMallocDefault));
     *F->status_host = 0;
     AIWC_HIP(hipEventCreateWithFlags(&F->done, hipEventDisableTiming));
+    AIWC_HIP(hipEventCreate(&F->grow_begin));
+    AIWC_HIP(hipEventCreate(&F->grow_end));
     {
       std::vector<int64_t> bases((size_t)n_tasks);
       for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
@@ -319,6 +322,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
       const int grid_max = grow_grid_size(cfg, n_tasks);
       DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
       launch_init(F->status.p, nullptr, s);
+      AIWC_HIP(hipEventRecord(F->grow_begin, s));
       for (int32_t f = 0; f < n_forests; ++f) {
         const int64_t t0 = F->first_task[f];
         const int32_t nt = params_host[f].num_trees;
@@ -326,9 +330,10 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         launch_init(nullptr, queue.p, s);
         launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
         launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid,
-                    s);
+                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, queue.p, F->status.p, scratch.p,
+                    n_cap, mtry_max, grid, s);
       }
+      AIWC_HIP(hipEventRecord(F->grow_end, s));
     } else {
       const int grid = grow_grid_size(cfg, n_tasks);
       DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
@@ -347,8 +352,8 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
           launch_init(F->status.p, queue.p, cs);
           launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, cs);
           launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                      F->nodes.p, F->node_N.p, F->n_nodes.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid,
-                      cs);
+                      F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, queue.p, F->status.p, scratch.p, n_cap,
+                      mtry_max, grid, cs);
         } catch (...) {
           (void)hipStreamEndCapture(cs, &graph);
           if (graph) (void)hipGraphDestroy(graph);
@@ -358,7 +363,10 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         }
         AIWC_HIP(hipStreamEndCapture(cs, &graph));
         AIWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        // timing events bracket the whole graph (initialise, prepare, grow)
+        AIWC_HIP(hipEventRecord(F->grow_begin, s));
         AIWC_HIP(hipGraphLaunch(exec, s));
+        AIWC_HIP(hipEventRecord(F->grow_end, s));
         AIWC_HIP(hipStreamSynchronize(s));
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
@@ -367,8 +375,11 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
       } else {
         launch_init(F->status.p, queue.p, s);
         launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
+        AIWC_HIP(hipEventRecord(F->grow_begin, s));
         launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max, grid, s);
+                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
+                    grid, s);
+        AIWC_HIP(hipEventRecord(F->grow_end, s));
       }
     }
     AIWC_HIP(hipMemcpyAsync(F->status_host, F->status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -413,6 +424,27 @@ int aiwc_rf_forest_info(const aiwc_rf_forest* f, int32_t forest_index, int32_t* 
       for (int32_t v : nn) tot += v;
       *total_nodes_host = tot;
     }
+  });
+}
+
+int aiwc_rf_forest_stats(const aiwc_rf_forest* f, int32_t forest_index, int64_t* work_host, float* grow_ms_host) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    std::string msg;
+    const int32_t code = resolve_status(f, msg);
+    if (code != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "fit failed: " + msg);
+    if (work_host) {
+      const int32_t nt = f->params[forest_index].num_trees;
+      std::vector<int64_t> w((size_t)nt * 4);
+      AIWC_HIP(hipMemcpy(w.data(), f->work.p + 4 * f->first_task[forest_index], sizeof(int64_t) * w.size(),
+                         hipMemcpyDeviceToHost));
+      for (int i = 0; i < 4; ++i) work_host[i] = 0;
+      for (int32_t t = 0; t < nt; ++t) {
+        for (int i = 0; i < 3; ++i) work_host[i] += w[4 * t + i];
+        work_host[3] = std::max(work_host[3], w[4 * t + 3]);
+      }
+    }
+    if (grow_ms_host) AIWC_HIP(hipEventElapsedTime(grow_ms_host, f->grow_begin, f->grow_end));
   });
 }
 
@@ -468,6 +500,8 @@ void aiwc_rf_forest_free(aiwc_rf_forest* f) {
   if (!f) return;
   (void)hipDeviceSynchronize();
   if (f->done) (void)hipEventDestroy(f->done);
+  if (f->grow_begin) (void)hipEventDestroy(f->grow_begin);
+  if (f->grow_end) (void)hipEventDestroy(f->grow_end);
   if (f->status_host) (void)hipHostFree(f->status_host);
   delete f;
 }

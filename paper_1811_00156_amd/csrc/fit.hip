@@ -116,6 +116,7 @@ struct GrowArgs {
   uint64_t* nodes;
   uint32_t* node_N;
   int32_t* n_nodes;
+  int64_t* work;  // per task: searched rows, searched nodes, partitioned rows, levels
   uint32_t* queue;
   uint32_t* status;
   uint8_t* scratch;
@@ -423,7 +424,9 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
   const int64_t base_node = T.node_base;
   uint32_t level_lo = 0, level_cnt = 1, next_id = 1;
   int cur = 0;
+  uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0;
   while (level_cnt > 0) {
+    ++levels;
     const int nxt = cur ^ 1;
     // (a) classify the level's nodes
     if (tid == 0) {
@@ -441,9 +444,13 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       } else if (len <= kSmallMax) {
         sc.status[k] = kSmall;
         sc.small[atomicAdd(&s_cnt[0], 1u)] = k;
+        work_rows += len;
+        ++work_nodes;
       } else {
         sc.status[k] = kBig;
         sc.big[atomicAdd(&s_cnt[1], 1u)] = k;
+        work_rows += len;
+        ++work_nodes;
       }
     }
     __syncthreads();
@@ -506,6 +513,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
             atomicOr(a.status, kStatusCapacity);
           }
           sc.rank[k] = r;
+          work_part += sc.mend[cur][k] - sc.mstart[cur][k];
           sc.curL[k] = sc.mstart[cur][k];
           sc.curR[k] = sc.mend[cur][k];
           const uint32_t NL = sc.dNL[k];
@@ -568,7 +576,17 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     next_id += 2 * n_split;
     cur = nxt;
   }
-  if (tid == 0) a.n_nodes[task_index] = (int32_t)next_id;
+  work_rows = block_sum<BLOCK, uint64_t>(work_rows, s_red);
+  work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, s_red);
+  work_part = block_sum<BLOCK, uint64_t>(work_part, s_red);
+  if (tid == 0) {
+    a.n_nodes[task_index] = (int32_t)next_id;
+    int64_t* wk = a.work + 4 * (int64_t)task_index;
+    wk[0] = (int64_t)work_rows;
+    wk[1] = (int64_t)work_nodes;
+    wk[2] = (int64_t)work_part;
+    wk[3] = (int64_t)levels;
+  }
 }
 
 template <int BLOCK>
@@ -672,8 +690,8 @@ int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks) {
 
 void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, uint32_t* d_queue, uint32_t* d_status,
-                 uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s) {
+                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint32_t* d_queue,
+                 uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s) {
   GrowArgs a;
   a.codes = codes;
   a.C = C;
@@ -685,6 +703,7 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const i
   a.nodes = nodes;
   a.node_N = node_N;
   a.n_nodes = n_nodes;
+  a.work = work;
   a.queue = d_queue;
   a.status = d_status;
   a.scratch = scratch;

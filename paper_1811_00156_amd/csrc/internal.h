@@ -118,10 +118,13 @@ struct aiwc_rf_forest {
   aiwc::DevBuf<uint64_t> nodes;            // node words, all slots
   aiwc::DevBuf<uint32_t> node_N;           // bootstrap weight per node
   aiwc::DevBuf<int32_t> n_nodes;           // per task
+  aiwc::DevBuf<int64_t> work;              // per task: searched rows, searched nodes, partitioned rows, levels
   aiwc::DevBuf<int64_t> node_base;         // per task, device copy for traversal
   aiwc::DevBuf<uint32_t> status;           // device status word
   uint32_t* status_host = nullptr;         // pinned
   hipEvent_t done = nullptr;
+  hipEvent_t grow_begin = nullptr;         // timing events around the tree-growing launch(es)
+  hipEvent_t grow_end = nullptr;
   int32_t fit_status = 0;                  // resolved status after wait
   bool waited = false;
   int64_t pool_nodes = 0;
@@ -152,8 +155,8 @@ size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks);
 void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, uint32_t* d_queue, uint32_t* d_status,
-                 uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s);
+                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint32_t* d_queue,
+                 uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s);
 
 // predict.hip
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,

@@ -52,6 +52,7 @@ _sig("aiwc_rf_fit", [_P, _i64, _i32, _P, _P, _P, _P, _P, _i32, _u32, _P, _P])
 _sig("aiwc_rf_forest_wait", [_P])
 _sig("aiwc_rf_forest_info", [_P, _i32, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_tree_sizes", [_P, _i32, _i32, _i32, _P])
+_sig("aiwc_rf_forest_stats", [_P, _i32, _P, _P])
 _sig("aiwc_rf_forest_export_host", [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_free", [_P], None)
 _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
@@ -65,7 +66,7 @@ _sig("aiwc_rf_server_free", [_P], None)
 _sig("aiwc_rf_last_error", [], ctypes.c_char_p)
 
 SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
-           "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_tree_sizes",
+           "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
            "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
@@ -183,6 +184,13 @@ class Forest:
         _check(_L.aiwc_rf_forest_info(self.handle, forest_index, None, None, None, ctypes.byref(tot)),
                "aiwc_rf_forest_info")
         return tot.value
+
+    def stats(self, forest_index: int = 0):
+        """(work, grow_ms): work = [searched rows, searched nodes, partitioned rows, max levels]."""
+        w = np.zeros(4, np.int64)
+        ms = ctypes.c_float()
+        _check(_L.aiwc_rf_forest_stats(self.handle, forest_index, _host(w), ctypes.byref(ms)), "aiwc_rf_forest_stats")
+        return w, ms.value
 
     def tree_sizes(self, forest_index: int = 0, tree_begin: int = 0, tree_end: int | None = None) -> np.ndarray:
         if tree_end is None:
