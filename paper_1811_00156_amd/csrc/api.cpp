@@ -66,11 +66,15 @@ int32_t status_to_code(uint32_t st, std::string& msg) {
   return AIWC_RF_OK;
 }
 
-GrowConfig grow_config(int64_t n_cap) {
+GrowConfig grow_config(int64_t n_cap, const std::vector<int32_t>& n_bins) {
   GrowConfig cfg;
   cfg.block = n_cap > 16384 ? 1024 : 512;
+  cfg.n_cap = n_cap;
+  cfg.bins_max = 1;
+  for (int32_t b : n_bins) cfg.bins_max = std::max(cfg.bins_max, b);
   if (const char* e = std::getenv("AIWC_RF_GROW_BLOCK")) cfg.block = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_GROW_WG_PER_CU")) cfg.wg_per_cu = std::atoi(e);
+  if (const char* e = std::getenv("AIWC_RF_HUGE_MIN")) cfg.huge_min = std::atoi(e);
   return cfg;
 }
 
@@ -313,20 +317,20 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     DevBuf<int64_t> y_fp((size_t)n, s);
     DevBuf<uint32_t> queue(1, s);
 
-    const GrowConfig cfg = grow_config(n_cap);
+    const GrowConfig cfg = grow_config(n_cap, binner->n_bins);
     const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
     const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
 
     if (plain) {
       // one launch sequence per forest, as separate fits would issue them
-      const int grid_max = grow_grid_size(cfg, n_tasks);
+      const int grid_max = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
       DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
       launch_init(F->status.p, nullptr, s);
       AIWC_HIP(hipEventRecord(F->grow_begin, s));
       for (int32_t f = 0; f < n_forests; ++f) {
         const int64_t t0 = F->first_task[f];
         const int32_t nt = params_host[f].num_trees;
-        const int grid = grow_grid_size(cfg, nt);
+        const int grid = grow_grid_size(cfg, nt, mtry_max, n_cols);
         launch_init(nullptr, queue.p, s);
         launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
         launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
@@ -335,7 +339,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
       }
       AIWC_HIP(hipEventRecord(F->grow_end, s));
     } else {
-      const int grid = grow_grid_size(cfg, n_tasks);
+      const int grid = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
       DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
       if (n_forests > 1) {
         // fused grid: the whole fit as one captured graph

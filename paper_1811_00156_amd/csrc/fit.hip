@@ -7,18 +7,24 @@
 // header):
 //   1. bootstrap: n_train Philox draws -> multiplicity per training row, then the
 //      in-bag rows are packed into 64-bit entries (row, weight, y_fp);
-//   2. for each level, every open node is classified (leaf by min.node.size or
-//      purity, or a split candidate); split candidates draw their mtry columns
-//      and search every (column, bin) for the largest S_L^2/N_L + S_R^2/N_R:
-//        - nodes with <= 64 in-bag rows: one wave per node, rows in lanes, the
-//          left sums of every lane's bin obtained by broadcasting each row;
-//        - larger nodes: one wave per (node, column) with a wave-private LDS
-//          histogram of (N, S, Q) per bin, then a wave prefix scan over bins;
+//   2. for each level, one thread per open node applies the leaf rules
+//      (min.node.size, purity) and draws the node's mtry candidate columns; the
+//      split search over every (candidate column, bin) is then tiered by the
+//      node's number of in-bag rows:
+//        - tiny  (<= 16 rows): one lane per (node, column), rows in registers,
+//          the left sums of every present code found by an all-pairs pass;
+//        - large (<= huge limit): one wave per (node, column), LDS histogram of
+//          (N, S, Q) per bin and a wave prefix scan over bins;
+//        - huge: the whole workgroup builds the LDS histograms of all candidate
+//          columns at once (each row's entry is read once), then one wave per
+//          column scans;
+//      every split maximises S_L^2/N_L + S_R^2/N_R; ties keep the lowest
+//      (column, bin);
 //   3. split nodes get breadth-first child ids from a workgroup scan, node words
 //      are written, and the in-bag entries are partitioned into the children's
-//      segments of the other entry buffer.
-// All sums are integers, the only floating point is the binary64 score, so the
-// order in which rows are visited never changes a result.
+//      segments of the other entry buffer (wave-aggregated cursor atomics).
+// All sums are integers and the only floating point is the binary64 score, so
+// the order in which rows are visited never changes a result.
 #include <limits.h>
 
 #include "device.h"
@@ -27,27 +33,36 @@
 namespace aiwc {
 namespace {
 
-constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kSplit = 3;
-constexpr uint32_t kSmallMax = 64;  // rows per node handled by the register method
+constexpr uint8_t kLeaf = 0, kTiny = 1, kBig = 2, kHuge = 3, kSplit = 4;
+constexpr uint32_t kTinyMax = 16;  // rows per node handled by the all-pairs lane method
+constexpr int kMaxBins = 256;
 
 struct Rec {
   double score;
   int64_t SL;
   uint64_t QL;
   uint32_t NL;
-  uint32_t colbin;  // column << 16 | bin
+  uint32_t colbin;  // column << 8 | bin
+};
+
+// Per-workgroup global scratch.  The per-level arrays come in two copies (the
+// level being grown and the next one), selected by the level parity without
+// indexing, so that every pointer stays in scalar registers.
+struct Level2 {
+  uint64_t* buf;
+  int32_t* slot;
+  uint32_t* mstart;
+  uint32_t* mend;
+  uint32_t* mN;
+  int64_t* mS;
+  uint64_t* mQ;
 };
 
 struct Scratch {
   uint32_t* cnt;
-  uint64_t* buf[2];
-  int32_t* slot[2];
-  uint32_t* mstart[2];
-  uint32_t* mend[2];
-  uint32_t* mN[2];
-  int64_t* mS[2];
-  uint64_t* mQ[2];
+  Level2 L0, L1;
   uint8_t* status;
+  uint8_t* cand;  // level node k's candidate columns at k * mtry, ascending
   uint8_t* dcol;
   uint8_t* dbin;
   uint32_t* dNL;
@@ -56,9 +71,10 @@ struct Scratch {
   uint32_t* rank;
   uint32_t* curL;
   uint32_t* curR;
-  uint32_t* small;
+  uint32_t* tiny;
   uint32_t* big;
-  Rec* recs;
+  uint32_t* huge;
+  Rec* recs;  // large node j's candidate i at j * mtry + i
 };
 
 __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max) {
@@ -69,17 +85,21 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
     return base + o;
   };
   const size_t n = (size_t)n_cap;
+  // large and huge nodes hold more than kTinyMax rows each
+  const size_t n_large = n / (kTinyMax + 1) + 1;
   s->cnt = reinterpret_cast<uint32_t*>(take(4 * n));
+  Level2* lv[2] = {&s->L0, &s->L1};
   for (int b = 0; b < 2; ++b) {
-    s->buf[b] = reinterpret_cast<uint64_t*>(take(8 * n));
-    s->slot[b] = reinterpret_cast<int32_t*>(take(4 * n));
-    s->mstart[b] = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->mend[b] = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->mN[b] = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->mS[b] = reinterpret_cast<int64_t*>(take(8 * n));
-    s->mQ[b] = reinterpret_cast<uint64_t*>(take(8 * n));
+    lv[b]->buf = reinterpret_cast<uint64_t*>(take(8 * n));
+    lv[b]->slot = reinterpret_cast<int32_t*>(take(4 * n));
+    lv[b]->mstart = reinterpret_cast<uint32_t*>(take(4 * n));
+    lv[b]->mend = reinterpret_cast<uint32_t*>(take(4 * n));
+    lv[b]->mN = reinterpret_cast<uint32_t*>(take(4 * n));
+    lv[b]->mS = reinterpret_cast<int64_t*>(take(8 * n));
+    lv[b]->mQ = reinterpret_cast<uint64_t*>(take(8 * n));
   }
   s->status = reinterpret_cast<uint8_t*>(take(n));
+  s->cand = reinterpret_cast<uint8_t*>(take(n * (size_t)mtry_max));
   s->dcol = reinterpret_cast<uint8_t*>(take(n));
   s->dbin = reinterpret_cast<uint8_t*>(take(n));
   s->dNL = reinterpret_cast<uint32_t*>(take(4 * n));
@@ -88,21 +108,19 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->small = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->big = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * (n / kSmallMax + 1) * (size_t)mtry_max));
+  s->tiny = reinterpret_cast<uint32_t*>(take(4 * n));
+  s->big = reinterpret_cast<uint32_t*>(take(4 * n_large));
+  s->huge = reinterpret_cast<uint32_t*>(take(4 * n_large));
+  s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   return off;
 }
 
-// Per-wave LDS: one histogram of (N, S, Q) over at most 256 bins and the
-// scratch of the mtry draw.
-struct WaveLds {
-  uint32_t hN[256];
-  uint64_t hS[256];
-  uint64_t hQ[256];
-  uint8_t perm[256];
-  uint8_t jidx[256];
-  uint32_t mask[8];
+// Per-wave LDS: one histogram of (N, S, Q) over at most 256 bins.  The tiny
+// method reuses it for the per-lane results.
+struct WaveHist {
+  uint32_t hN[kMaxBins];
+  uint64_t hS[kMaxBins];
+  uint64_t hQ[kMaxBins];
 };
 
 struct GrowArgs {
@@ -122,217 +140,14 @@ struct GrowArgs {
   uint8_t* scratch;
   int64_t n_cap;
   int32_t mtry_max;
+  int32_t huge_min;   // nodes with more rows than this use the workgroup-wide histogram
+  int32_t bstride;    // bins per column histogram in the workgroup-wide layout
+  int32_t huge_cols;  // columns whose histograms fit the LDS at once
   size_t scratch_stride;
-};
-
-// Everything a wave task needs about the level being grown.
-struct Level {
-  const uint64_t* buf;
-  const uint32_t* mstart;
-  const uint32_t* mend;
-  const uint32_t* mN;
-  const int64_t* mS;
-  uint32_t level_lo;
+  uint32_t union_bytes;  // dynamic LDS
 };
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ int64_t readlane64(int64_t v, uint32_t j) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, j);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), j);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// The mtry candidate columns of node `node` of tree `tree`: a partial
-// Fisher-Yates shuffle of 0..C-1 driven by draws k = 0..mtry-1 of the stream
-// (seed, tag 1, node, tree); position k swaps with k + floor(r_k (C-k) / 2^64).
-// The chosen set is left in L.mask (bit c = column c chosen).
-__device__ void draw_candidates(WaveLds& L, uint64_t seed, uint32_t node, uint32_t tree, int C, int mtry) {
-  const int lane = (int)lane_id();
-  const int nblk = (mtry + 3) >> 2;
-  for (int b = lane; b < nblk; b += kWave) {
-    const U64x4 r = philox4x64_10((uint64_t)b, kTagMtry, node, tree, seed, 0);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int k = 4 * b + w;
-      if (k < mtry) L.jidx[k] = (uint8_t)(k + (int)scale_draw(r.w[w], (uint64_t)(C - k)));
-    }
-  }
-  for (int c = lane; c < C; c += kWave) L.perm[c] = (uint8_t)c;
-  if (lane < 8) L.mask[lane] = 0;
-  wave_lds_sync();
-  if (lane == 0) {
-    for (int k = 0; k < mtry; ++k) {
-      const int j = L.jidx[k];
-      const uint8_t t = L.perm[k];
-      L.perm[k] = L.perm[j];
-      L.perm[j] = t;
-    }
-  }
-  wave_lds_sync();
-  for (int k = lane; k < mtry; k += kWave) {
-    const uint32_t c = L.perm[k];
-    atomicOr(&L.mask[c >> 5], 1u << (c & 31));
-  }
-  wave_lds_sync();
-}
-
-// Split search of a node with at most 64 in-bag rows, whole node in one wave.
-__device__ void small_node(const GrowArgs& a, const TreeTask& T, const Scratch& sc, const Level& lv, WaveLds& L,
-                           uint32_t k) {
-  const int lane = (int)lane_id();
-  const uint32_t start = rfl(lv.mstart[k]);
-  const uint32_t len = rfl(lv.mend[k]) - start;
-  const uint32_t N = rfl(lv.mN[k]);
-  const int64_t S = lv.mS[k];
-  draw_candidates(L, T.seed, lv.level_lo + k, (uint32_t)T.tree, a.C, T.mtry);
-
-  const bool valid = (uint32_t)lane < len;
-  const uint64_t e = valid ? lv.buf[start + lane] : 0;
-  const uint32_t w = valid ? entry_w(e) : 0;
-  const int64_t y = entry_y(e);
-  const int64_t wy = (int64_t)w * y;
-  const uint8_t* rowp = a.codes + (size_t)entry_row(e) * a.C;
-
-  double best = -1.0;
-  int32_t best_col = -1, best_bin = 0;
-  uint32_t best_NL = 0, best_code = 0;
-  int64_t best_SL = 0;
-  for (int mw = 0; mw < 8; ++mw) {
-    uint32_t m = rfl(L.mask[mw]);
-    while (m) {
-      const int c = mw * 32 + __builtin_ctz(m);
-      m &= m - 1;
-      const uint32_t code = valid ? rowp[c] : 0u;
-      uint32_t NL = 0;
-      int64_t SL = 0;
-      for (uint32_t j = 0; j < len; ++j) {
-        const uint32_t cj = __builtin_amdgcn_readlane(code, j);
-        const uint32_t wj = __builtin_amdgcn_readlane(w, j);
-        const int64_t sj = readlane64(wy, j);
-        if (cj <= code) {
-          NL += wj;
-          SL += sj;
-        }
-      }
-      double s = -1.0;
-      if (valid && NL < N) s = split_score(SL, NL, S - SL, N - NL);
-      const ArgMax am = wave_argmax(s, (int32_t)code);
-      if (am.score > best) {
-        best = am.score;
-        best_col = c;
-        best_bin = am.key;
-        best_NL = __shfl(NL, am.lane, kWave);
-        best_SL = __shfl(SL, am.lane, kWave);
-        best_code = code;
-      }
-    }
-  }
-  if (best_col >= 0 && best - parent_score(S, N) > 0.0) {
-    uint64_t ql = (valid && best_code <= (uint32_t)best_bin) ? (uint64_t)(wy * y) : 0ull;
-    ql = wave_sum(ql);
-    if (lane == 0) {
-      sc.dcol[k] = (uint8_t)best_col;
-      sc.dbin[k] = (uint8_t)best_bin;
-      sc.dNL[k] = best_NL;
-      sc.dSL[k] = best_SL;
-      sc.dQL[k] = ql;
-      sc.status[k] = kSplit;
-    }
-  } else if (lane == 0) {
-    sc.status[k] = kLeaf;
-  }
-}
-
-// Best bin of candidate column number `ci` of a node with more than 64 in-bag
-// rows: LDS histogram of (N, S, Q), wave prefix scan over bins, binary64 score.
-__device__ void big_column(const GrowArgs& a, const TreeTask& T, const Scratch& sc, const Level& lv, WaveLds& L,
-                           uint32_t j, int ci) {
-  const int lane = (int)lane_id();
-  const uint32_t k = rfl(sc.big[j]);
-  const uint32_t start = rfl(lv.mstart[k]);
-  const uint32_t end = rfl(lv.mend[k]);
-  const uint32_t N = rfl(lv.mN[k]);
-  draw_candidates(L, T.seed, lv.level_lo + k, (uint32_t)T.tree, a.C, T.mtry);
-  int c = -1;
-  {
-    int seen = 0;
-    for (int mw = 0; mw < 8 && c < 0; ++mw) {
-      uint32_t m = rfl(L.mask[mw]);
-      while (m) {
-        const int cc = mw * 32 + __builtin_ctz(m);
-        m &= m - 1;
-        if (seen++ == ci) {
-          c = cc;
-          break;
-        }
-      }
-    }
-  }
-  const int B = a.n_bins[c];
-  for (int b = lane; b < B; b += kWave) {
-    L.hN[b] = 0;
-    L.hS[b] = 0;
-    L.hQ[b] = 0;
-  }
-  wave_lds_sync();
-  for (uint32_t p = start + lane; p < end; p += kWave) {
-    const uint64_t e = lv.buf[p];
-    const uint32_t w = entry_w(e);
-    const int64_t y = entry_y(e);
-    const uint32_t code = a.codes[(size_t)entry_row(e) * a.C + c];
-    const int64_t wy = (int64_t)w * y;
-    atomicAdd(&L.hN[code], w);
-    atomicAdd((unsigned long long*)&L.hS[code], (unsigned long long)wy);
-    atomicAdd((unsigned long long*)&L.hQ[code], (unsigned long long)(wy * y));
-  }
-  wave_lds_sync();
-  const int R = (B + kWave - 1) / kWave;
-  const int b0 = lane * R;
-  const int b1 = min(b0 + R, B);
-  uint32_t n_loc = 0;
-  int64_t s_loc = 0;
-  uint64_t q_loc = 0;
-  for (int b = b0; b < b1; ++b) {
-    n_loc += L.hN[b];
-    s_loc += (int64_t)L.hS[b];
-    q_loc += L.hQ[b];
-  }
-  uint32_t NL = wave_incl_scan_u32(n_loc) - n_loc;
-  int64_t SL = wave_incl_scan<int64_t>(s_loc) - s_loc;
-  uint64_t QL = wave_incl_scan<uint64_t>(q_loc) - q_loc;
-  const int64_t S = lv.mS[k];
-  double lbest = -1.0;
-  int32_t lbin = INT_MAX;
-  uint32_t lNL = 0;
-  int64_t lSL = 0;
-  uint64_t lQL = 0;
-  for (int b = b0; b < b1; ++b) {
-    NL += L.hN[b];
-    SL += (int64_t)L.hS[b];
-    QL += L.hQ[b];
-    if (b <= B - 2 && NL > 0 && NL < N) {
-      const double s = split_score(SL, NL, S - SL, N - NL);
-      if (s > lbest) {
-        lbest = s;
-        lbin = b;
-        lNL = NL;
-        lSL = SL;
-        lQL = QL;
-      }
-    }
-  }
-  const ArgMax am = wave_argmax(lbest, lbin);
-  if (lane == am.lane) {
-    Rec r;
-    r.score = am.score;
-    r.SL = lSL;
-    r.QL = lQL;
-    r.NL = lNL;
-    r.colbin = ((uint32_t)c << 16) | (uint32_t)(am.score >= 0.0 ? lbin : 0);
-    sc.recs[(size_t)j * T.mtry + ci] = r;
-  }
-}
 
 // Workgroup exclusive scan of one u32 per thread; `total` receives the sum.
 template <int BLOCK>
@@ -368,13 +183,377 @@ __device__ __forceinline__ T block_sum(T v, T* tmp) {
   return s;
 }
 
+// The mtry candidate columns of node `node` of tree `tree`, drawn by one
+// thread: a partial Fisher-Yates shuffle of 0..C-1 driven by draws k = 0 ..
+// mtry-1 of the stream (seed, tag 1, node, tree); position k swaps with
+// k + floor(r_k (C-k) / 2^64).  `perm` is this thread's C-entry LDS row
+// (stride `pst` bytes between entries).  The chosen columns are written
+// ascending to `out`.
+__device__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t node, uint32_t tree, int C, int mtry,
+                                uint8_t* out) {
+  for (int c = 0; c < C; ++c) perm[c * pst] = (uint8_t)c;
+  uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+  for (int b = 0; 4 * b < mtry; ++b) {
+    const U64x4 r = philox4x64_10((uint64_t)b, kTagMtry, node, tree, seed, 0);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int k = 4 * b + w;
+      if (k < mtry) {
+        const int j = k + (int)scale_draw(r.w[w], (uint64_t)(C - k));
+        const uint8_t vk = perm[k * pst], vj = perm[j * pst];
+        perm[k * pst] = vj;
+        perm[j * pst] = vk;
+        const uint64_t bit = 1ull << (vj & 63);
+        switch (vj >> 6) {
+          case 0: m0 |= bit; break;
+          case 1: m1 |= bit; break;
+          case 2: m2 |= bit; break;
+          default: m3 |= bit; break;
+        }
+      }
+    }
+  }
+  int i = 0;
+  for (uint64_t m = m0; m; m &= m - 1) out[i++] = (uint8_t)__builtin_ctzll(m);
+  for (uint64_t m = m1; m; m &= m - 1) out[i++] = (uint8_t)(64 + __builtin_ctzll(m));
+  for (uint64_t m = m2; m; m &= m - 1) out[i++] = (uint8_t)(128 + __builtin_ctzll(m));
+  for (uint64_t m = m3; m; m &= m - 1) out[i++] = (uint8_t)(192 + __builtin_ctzll(m));
+}
+
+// Best split of one column for a node of at most L rows held in registers,
+// cw[r] = code << 24 | weight and wy[r] = weight * y_fp: for every row a, the
+// left side is every row whose code is <= code[a].
+template <int L>
+__device__ __forceinline__ void tiny_column(const uint32_t (&cw)[kTinyMax], const int64_t (&wy)[kTinyMax], uint32_t len,
+                                            uint32_t N, int64_t S, uint32_t col, double& best, uint32_t& best_cb) {
+#pragma unroll
+  for (int a = 0; a < L; ++a) {
+    if ((uint32_t)a < len) {
+      const uint32_t ca = cw[a] >> 24;
+      uint32_t NL = 0;
+      int64_t SL = 0;
+#pragma unroll
+      for (int b = 0; b < L; ++b) {
+        const bool in = (uint32_t)b < len && (cw[b] >> 24) <= ca;
+        NL += in ? (cw[b] & 0xFFFFFFu) : 0u;
+        SL += in ? wy[b] : 0;
+      }
+      if (NL < N) {
+        const double s = split_score(SL, NL, S - SL, N - NL);
+        const uint32_t cb = (col << 8) | ca;
+        if (s > best || (s == best && cb < best_cb)) {
+          best = s;
+          best_cb = cb;
+        }
+      }
+    }
+  }
+}
+
+struct Ctx {
+  const GrowArgs* a;
+  const TreeTask* T;
+  Scratch sc;
+  const uint64_t* buf;  // this level's entries
+  const uint32_t* mstart;
+  const uint32_t* mend;
+  const uint32_t* mN;
+  const int64_t* mS;
+  const uint64_t* mQ;
+};
+
+// Tiny nodes: a wave takes P = 64 / G nodes (G = min(mtry, 64) lanes each);
+// lane (g, i) evaluates candidate columns i, i + G, ... of node g, then the
+// group's first lane combines the group (max score, then lowest (column, bin))
+// and decides the node.  Each lane keeps its node's row ids in its own column
+// of the wave's LDS area and the (code, weight, weight * y) of the column being
+// evaluated in registers.
+__device__ void tiny_task(const Ctx& x, uint32_t t, uint32_t n_tiny, WaveHist& wl) {
+  const GrowArgs& a = *x.a;
+  const int mtry = x.T->mtry;
+  const int lane = (int)lane_id();
+  const int G = mtry < kWave ? mtry : kWave;
+  const int P = kWave / G;
+  const int g = lane / G, i0 = lane % G;
+  const uint32_t idx = t * (uint32_t)P + (uint32_t)g;
+  const bool active = g < P && idx < n_tiny;
+  const uint32_t k = active ? x.sc.tiny[idx] : 0u;
+  const uint32_t start = active ? x.mstart[k] : 0u;
+  const uint32_t len = active ? x.mend[k] - start : 0u;
+  const uint32_t N = active ? x.mN[k] : 0u;
+  const int64_t S = active ? x.mS[k] : 0;
+  uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
+  uint32_t* rows = reinterpret_cast<uint32_t*>(area);              // [kTinyMax][64]
+  double* s_score = reinterpret_cast<double*>(area + 4096);        // [64]
+  uint32_t* s_cb = reinterpret_cast<uint32_t*>(area + 4096 + 512);  // [64]
+
+  uint32_t cw[kTinyMax];
+  int64_t wy[kTinyMax];
+#pragma unroll
+  for (int r = 0; r < (int)kTinyMax; ++r) {
+    const uint64_t e = (uint32_t)r < len ? x.buf[start + r] : 0ull;
+    const uint32_t w = (uint32_t)r < len ? entry_w(e) : 0u;
+    rows[r * kWave + lane] = entry_row(e);
+    cw[r] = w;
+    wy[r] = (int64_t)w * entry_y(e);
+  }
+  double best = -1.0;
+  uint32_t best_cb = 0xFFFFFFFFu;
+  // one unrolled loop length per wave; shorter nodes are predicated
+  uint32_t lmax = len;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, d, kWave));
+  lmax = rfl(lmax);
+  for (int i = i0; active && i < mtry; i += G) {
+    const uint32_t c = x.sc.cand[(size_t)k * mtry + i];
+#pragma unroll
+    for (int r = 0; r < (int)kTinyMax; ++r) {
+      const uint32_t code = (uint32_t)r < len ? a.codes[(size_t)rows[r * kWave + lane] * a.C + c] : 0u;
+      cw[r] = (cw[r] & 0xFFFFFFu) | (code << 24);
+    }
+    if (lmax <= 4)
+      tiny_column<4>(cw, wy, len, N, S, c, best, best_cb);
+    else if (lmax <= 8)
+      tiny_column<8>(cw, wy, len, N, S, c, best, best_cb);
+    else
+      tiny_column<16>(cw, wy, len, N, S, c, best, best_cb);
+  }
+  // combine each group in LDS
+  s_score[lane] = best;
+  s_cb[lane] = best_cb;
+  wave_lds_sync();
+  if (active && i0 == 0) {
+    for (int j = 1; j < G; ++j) {
+      const double s = s_score[lane + j];
+      const uint32_t cb = s_cb[lane + j];
+      if (s > best || (s == best && cb < best_cb)) {
+        best = s;
+        best_cb = cb;
+      }
+    }
+    if (best >= 0.0 && best - parent_score(S, N) > 0.0) {
+      const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+      uint32_t NL = 0;
+      int64_t SL = 0;
+      uint64_t QL = 0;
+      for (uint32_t r = 0; r < len; ++r) {
+        const uint64_t e = x.buf[start + r];
+        if (a.codes[(size_t)entry_row(e) * a.C + col] <= bin) {
+          const int64_t ww = (int64_t)entry_w(e), y = entry_y(e);
+          NL += (uint32_t)ww;
+          SL += ww * y;
+          QL += (uint64_t)(ww * y * y);
+        }
+      }
+      x.sc.dcol[k] = (uint8_t)col;
+      x.sc.dbin[k] = (uint8_t)bin;
+      x.sc.dNL[k] = NL;
+      x.sc.dSL[k] = SL;
+      x.sc.dQL[k] = QL;
+      x.sc.status[k] = kSplit;
+    } else {
+      x.sc.status[k] = kLeaf;
+    }
+  }
+  wave_lds_sync();
+}
+
+// Scan one column's histogram (B bins) with a wave: lane l owns bins
+// [l R, (l+1) R); prefix sums give the left side of every split b <= B-2.
+// Returns the wave's best (max score, lowest bin) in every lane; the left
+// sums oNL, oSL, oQL of that split are valid in lane `am.lane`.
+__device__ __forceinline__ ArgMax scan_column(const uint32_t* hN, const uint64_t* hS, const uint64_t* hQ, int B,
+                                              uint32_t N, int64_t S, uint32_t& oNL, int64_t& oSL, uint64_t& oQL) {
+  const int lane = (int)lane_id();
+  const int R = (B + kWave - 1) / kWave;
+  const int b0 = lane * R;
+  const int b1 = min(b0 + R, B);
+  uint32_t n_loc = 0;
+  int64_t s_loc = 0;
+  uint64_t q_loc = 0;
+  for (int b = b0; b < b1; ++b) {
+    n_loc += hN[b];
+    s_loc += (int64_t)hS[b];
+    q_loc += hQ[b];
+  }
+  uint32_t NL = wave_incl_scan_u32(n_loc) - n_loc;
+  int64_t SL = wave_incl_scan<int64_t>(s_loc) - s_loc;
+  uint64_t QL = wave_incl_scan<uint64_t>(q_loc) - q_loc;
+  double lbest = -1.0;
+  int32_t lbin = INT_MAX;
+  oNL = 0;
+  oSL = 0;
+  oQL = 0;
+  for (int b = b0; b < b1; ++b) {
+    NL += hN[b];
+    SL += (int64_t)hS[b];
+    QL += hQ[b];
+    if (b <= B - 2 && NL > 0 && NL < N) {
+      const double s = split_score(SL, NL, S - SL, N - NL);
+      if (s > lbest) {
+        lbest = s;
+        lbin = b;
+        oNL = NL;
+        oSL = SL;
+        oQL = QL;
+      }
+    }
+  }
+  return wave_argmax(lbest, lbin);
+}
+
+// Large nodes: one wave per (node, candidate column) with an LDS histogram.
+__device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
+  const GrowArgs& a = *x.a;
+  const int lane = (int)lane_id();
+  const int mtry = x.T->mtry;
+  const uint32_t k = rfl(x.sc.big[j]);
+  const uint32_t start = rfl(x.mstart[k]);
+  const uint32_t end = rfl(x.mend[k]);
+  const uint32_t N = rfl(x.mN[k]);
+  const int64_t S = x.mS[k];
+  const int c = (int)rfl(x.sc.cand[(size_t)k * mtry + ci]);
+  const int B = a.n_bins[c];
+  for (int b = lane; b < B; b += kWave) {
+    L.hN[b] = 0;
+    L.hS[b] = 0;
+    L.hQ[b] = 0;
+  }
+  wave_lds_sync();
+  for (uint32_t p = start + lane; p < end; p += kWave) {
+    const uint64_t e = x.buf[p];
+    const uint32_t w = entry_w(e);
+    const int64_t y = entry_y(e);
+    const uint32_t code = a.codes[(size_t)entry_row(e) * a.C + c];
+    const int64_t wy = (int64_t)w * y;
+    atomicAdd(&L.hN[code], w);
+    atomicAdd((unsigned long long*)&L.hS[code], (unsigned long long)wy);
+    atomicAdd((unsigned long long*)&L.hQ[code], (unsigned long long)(wy * y));
+  }
+  wave_lds_sync();
+  uint32_t NL;
+  int64_t SL;
+  uint64_t QL;
+  const ArgMax am = scan_column(L.hN, L.hS, L.hQ, B, N, S, NL, SL, QL);
+  if (lane == am.lane) {
+    Rec r;
+    r.score = am.score;
+    r.SL = SL;
+    r.QL = QL;
+    r.NL = NL;
+    r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
+    x.sc.recs[(size_t)j * mtry + ci] = r;
+  }
+  wave_lds_sync();
+}
+
+// Decide a node from its per-column records (columns ascending: keep the
+// first strictly greater score).
+__device__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int mtry) {
+  double best = -1.0;
+  int bi = -1;
+  for (int i = 0; i < mtry; ++i) {
+    const double s = recs[i].score;
+    if (s > best) {
+      best = s;
+      bi = i;
+    }
+  }
+  const int64_t S = x.mS[k];
+  const uint32_t N = x.mN[k];
+  if (bi >= 0 && best - parent_score(S, N) > 0.0) {
+    const Rec r = recs[bi];
+    x.sc.dcol[k] = (uint8_t)(r.colbin >> 8);
+    x.sc.dbin[k] = (uint8_t)(r.colbin & 0xFF);
+    x.sc.dNL[k] = r.NL;
+    x.sc.dSL[k] = r.SL;
+    x.sc.dQL[k] = r.QL;
+    x.sc.status[k] = kSplit;
+  } else {
+    x.sc.status[k] = kLeaf;
+  }
+}
+
+struct Shared {
+  uint32_t tmp[17];
+  uint64_t red[16];
+  uint32_t cnt[3];
+  uint32_t task;
+  uint8_t cand[256];
+  Rec recs[256];
+};
+
+// Huge node: every thread adds its rows into the histograms of up to
+// huge_cols candidate columns at once (all mtry in one pass when they fit);
+// one wave per column then scans.
 template <int BLOCK>
-__device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, WaveLds* wl,
-                          uint32_t* s_tmp, uint64_t* s_red, uint32_t* s_cnt) {
+__device__ void huge_node(const Ctx& x, uint32_t k, uint8_t* lds, Shared& sh) {
   constexpr int NW = BLOCK / kWave;
-  const int tid = threadIdx.x, wid = tid / kWave;
+  const GrowArgs& a = *x.a;
+  const int mtry = x.T->mtry;
+  const int bs = a.bstride, hc = a.huge_cols;
+  const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
+  uint32_t* hN = reinterpret_cast<uint32_t*>(lds);
+  uint64_t* hS = reinterpret_cast<uint64_t*>(lds + (size_t)4 * hc * bs);
+  uint64_t* hQ = hS + (size_t)hc * bs;
+  for (int i = tid; i < mtry; i += BLOCK) sh.cand[i] = x.sc.cand[(size_t)k * mtry + i];
+  const uint32_t start = x.mstart[k], end = x.mend[k];
+  const uint32_t N = x.mN[k];
+  const int64_t S = x.mS[k];
+  for (int c0 = 0; c0 < mtry; c0 += hc) {
+    const int nc = min(hc, mtry - c0);
+    for (int i = tid; i < nc * bs; i += BLOCK) {
+      hN[i] = 0;
+      hS[i] = 0;
+      hQ[i] = 0;
+    }
+    __syncthreads();
+    for (uint32_t p = start + tid; p < end; p += BLOCK) {
+      const uint64_t e = x.buf[p];
+      const uint32_t w = entry_w(e);
+      const int64_t y = entry_y(e);
+      const int64_t wy = (int64_t)w * y;
+      const uint64_t wyy = (uint64_t)(wy * y);
+      const uint8_t* rp = a.codes + (size_t)entry_row(e) * a.C;
+      for (int i = 0; i < nc; ++i) {
+        const int h = i * bs + rp[sh.cand[c0 + i]];
+        atomicAdd(&hN[h], w);
+        atomicAdd((unsigned long long*)&hS[h], (unsigned long long)wy);
+        atomicAdd((unsigned long long*)&hQ[h], (unsigned long long)wyy);
+      }
+    }
+    __syncthreads();
+    for (int i = wid; i < nc; i += NW) {
+      const int c = sh.cand[c0 + i];
+      const int B = a.n_bins[c];
+      uint32_t NL;
+      int64_t SL;
+      uint64_t QL;
+      const ArgMax am = scan_column(hN + i * bs, hS + i * bs, hQ + i * bs, B, N, S, NL, SL, QL);
+      if (lane == am.lane) {
+        Rec r;
+        r.score = am.score;
+        r.SL = SL;
+        r.QL = QL;
+        r.NL = NL;
+        r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
+        sh.recs[c0 + i] = r;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) decide_from_recs(x, k, sh.recs, mtry);
+  __syncthreads();
+}
+
+template <int BLOCK>
+__device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, uint8_t* lds,
+                          Shared& sh) {
+  constexpr int NW = BLOCK / kWave;
+  const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
   const int64_t n = T.n_train;
   const int32_t* train = T.train_off >= 0 ? a.train_rows + T.train_off : nullptr;
+  const int mtry = T.mtry;
 
   // 1. bootstrap multiplicities
   for (int64_t i = tid; i < n; i += BLOCK) sc.cnt[i] = T.bootstrap ? 0u : 1u;
@@ -397,114 +576,108 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     const int64_t i = base + tid;
     const uint32_t c = i < n ? sc.cnt[i] : 0u;
     uint32_t total;
-    const uint32_t pos = block_exscan<BLOCK>(c > 0 ? 1u : 0u, s_tmp, total) + n_inbag;
+    const uint32_t pos = block_exscan<BLOCK>(c > 0 ? 1u : 0u, sh.tmp, total) + n_inbag;
     if (c > 0) {
       const uint32_t row = train ? (uint32_t)train[i] : (uint32_t)i;
       const int64_t y = a.y_fp[row];
-      sc.buf[0][pos] = entry_pack(row, c, y);
-      sc.slot[0][pos] = 0;
+      sc.L0.buf[pos] = entry_pack(row, c, y);
+      sc.L0.slot[pos] = 0;
       N0 += c;
       S0 += (int64_t)c * y;
       Q0 += (uint64_t)((int64_t)c * y * y);
     }
     n_inbag += total;
   }
-  N0 = block_sum<BLOCK, uint64_t>(N0, s_red);
-  S0 = (int64_t)block_sum<BLOCK, uint64_t>((uint64_t)S0, s_red);
-  Q0 = block_sum<BLOCK, uint64_t>(Q0, s_red);
+  N0 = block_sum<BLOCK, uint64_t>(N0, sh.red);
+  S0 = (int64_t)block_sum<BLOCK, uint64_t>((uint64_t)S0, sh.red);
+  Q0 = block_sum<BLOCK, uint64_t>(Q0, sh.red);
   if (tid == 0) {
-    sc.mstart[0][0] = 0;
-    sc.mend[0][0] = n_inbag;
-    sc.mN[0][0] = (uint32_t)N0;
-    sc.mS[0][0] = S0;
-    sc.mQ[0][0] = Q0;
+    sc.L0.mstart[0] = 0;
+    sc.L0.mend[0] = n_inbag;
+    sc.L0.mN[0] = (uint32_t)N0;
+    sc.L0.mS[0] = S0;
+    sc.L0.mQ[0] = Q0;
   }
   __syncthreads();
 
+  // threads that draw candidates each own a C-byte row of the LDS union area
+  const int n_draw = min(BLOCK, (int)(a.union_bytes / (uint32_t)a.C));
   const int64_t base_node = T.node_base;
   uint32_t level_lo = 0, level_cnt = 1, next_id = 1;
   int cur = 0;
   uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0;
   while (level_cnt > 0) {
     ++levels;
-    const int nxt = cur ^ 1;
-    // (a) classify the level's nodes
+    const Level2 C = cur ? sc.L1 : sc.L0;  // this level
+    const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
+    const Ctx x{&a, &T, sc, C.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
+    // (a) leaf rules, candidate draws, tiers
     if (tid == 0) {
-      s_cnt[0] = 0;
-      s_cnt[1] = 0;
+      sh.cnt[0] = 0;
+      sh.cnt[1] = 0;
+      sh.cnt[2] = 0;
     }
     __syncthreads();
-    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-      const uint32_t N = sc.mN[cur][k];
-      const int64_t S = sc.mS[cur][k];
-      const uint64_t Q = sc.mQ[cur][k];
-      const uint32_t len = sc.mend[cur][k] - sc.mstart[cur][k];
-      if ((int64_t)N <= T.min_node || node_is_pure(N, S, Q)) {
-        sc.status[k] = kLeaf;
-      } else if (len <= kSmallMax) {
-        sc.status[k] = kSmall;
-        sc.small[atomicAdd(&s_cnt[0], 1u)] = k;
+    if (tid < n_draw) {
+      for (uint32_t k = tid; k < level_cnt; k += n_draw) {
+        const uint32_t N = x.mN[k];
+        const int64_t S = x.mS[k];
+        const uint64_t Q = x.mQ[k];
+        const uint32_t len = x.mend[k] - x.mstart[k];
+        if ((int64_t)N <= T.min_node || node_is_pure(N, S, Q)) {
+          sc.status[k] = kLeaf;
+          continue;
+        }
+        draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                        sc.cand + (size_t)k * mtry);
         work_rows += len;
         ++work_nodes;
-      } else {
-        sc.status[k] = kBig;
-        sc.big[atomicAdd(&s_cnt[1], 1u)] = k;
-        work_rows += len;
-        ++work_nodes;
-      }
-    }
-    __syncthreads();
-    const uint32_t n_small = s_cnt[0], n_big = s_cnt[1];
-    const Level lv{sc.buf[cur], sc.mstart[cur], sc.mend[cur], sc.mN[cur], sc.mS[cur], level_lo};
-    // (b) split search
-    const uint32_t n_big_tasks = n_big * (uint32_t)T.mtry;
-    const uint32_t n_tasks = n_big_tasks + n_small;
-    for (uint32_t t = wid; t < n_tasks; t += NW) {
-      if (t < n_big_tasks)
-        big_column(a, T, sc, lv, wl[wid], t / T.mtry, (int)(t % T.mtry));
-      else
-        small_node(a, T, sc, lv, wl[wid], sc.small[t - n_big_tasks]);
-    }
-    __syncthreads();
-    // (c) decisions of the large nodes
-    for (uint32_t j = tid; j < n_big; j += BLOCK) {
-      const uint32_t k = sc.big[j];
-      double best = -1.0;
-      int bi = -1;
-      for (int i = 0; i < T.mtry; ++i) {
-        const double s = sc.recs[(size_t)j * T.mtry + i].score;
-        if (s > best) {
-          best = s;
-          bi = i;
+        if (len <= kTinyMax) {
+          sc.status[k] = kTiny;
+          sc.tiny[atomicAdd(&sh.cnt[0], 1u)] = k;
+        } else if ((int32_t)len <= a.huge_min) {
+          sc.status[k] = kBig;
+          sc.big[atomicAdd(&sh.cnt[1], 1u)] = k;
+        } else {
+          sc.status[k] = kHuge;
+          sc.huge[atomicAdd(&sh.cnt[2], 1u)] = k;
         }
       }
-      const int64_t S = sc.mS[cur][k];
-      const uint32_t N = sc.mN[cur][k];
-      if (bi >= 0 && best - parent_score(S, N) > 0.0) {
-        const Rec r = sc.recs[(size_t)j * T.mtry + bi];
-        sc.dcol[k] = (uint8_t)(r.colbin >> 16);
-        sc.dbin[k] = (uint8_t)(r.colbin & 0xFFFF);
-        sc.dNL[k] = r.NL;
-        sc.dSL[k] = r.SL;
-        sc.dQL[k] = r.QL;
-        sc.status[k] = kSplit;
-      } else {
-        sc.status[k] = kLeaf;
+    }
+    __syncthreads();
+    const uint32_t n_tiny = sh.cnt[0], n_big = sh.cnt[1], n_huge = sh.cnt[2];
+    // (b) huge nodes, one after another, with the whole workgroup
+    for (uint32_t h = 0; h < n_huge; ++h) huge_node<BLOCK>(x, sc.huge[h], lds, sh);
+    // (c) large-node columns and tiny-node groups, one wave each
+    {
+      const int G = mtry < kWave ? mtry : kWave;
+      const uint32_t P = (uint32_t)(kWave / G);
+      const uint32_t n_big_tasks = n_big * (uint32_t)mtry;
+      const uint32_t n_tiny_tasks = (n_tiny + P - 1) / P;
+      WaveHist& wl = reinterpret_cast<WaveHist*>(lds)[wid];
+      for (uint32_t t = wid; t < n_big_tasks + n_tiny_tasks; t += NW) {
+        if (t < n_big_tasks)
+          big_task(x, t / mtry, (int)(t % mtry), wl);
+        else
+          tiny_task(x, t - n_big_tasks, n_tiny, wl);
       }
     }
     __syncthreads();
-    // (d) breadth-first child ids, node words, children's sums and cursors
+    // (d) decisions of the large nodes
+    for (uint32_t j = tid; j < n_big; j += BLOCK) decide_from_recs(x, sc.big[j], sc.recs + (size_t)j * mtry, mtry);
+    __syncthreads();
+    // (e) breadth-first child ids, node words, children's sums and cursors
     uint32_t n_split = 0;
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
       const uint32_t k = b0 + tid;
       const bool in = k < level_cnt;
       const bool split = in && sc.status[k] == kSplit;
       uint32_t total;
-      const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, s_tmp, total) + n_split;
+      const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, sh.tmp, total) + n_split;
       if (in) {
         const uint32_t node = level_lo + k;
-        const uint32_t N = sc.mN[cur][k];
-        const int64_t S = sc.mS[cur][k];
+        const uint32_t N = x.mN[k];
+        const int64_t S = x.mS[k];
         if (split) {
           const uint32_t left = next_id + 2 * r;
           if ((int64_t)left + 1 < T.capacity) {
@@ -513,20 +686,21 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
             atomicOr(a.status, kStatusCapacity);
           }
           sc.rank[k] = r;
-          work_part += sc.mend[cur][k] - sc.mstart[cur][k];
-          sc.curL[k] = sc.mstart[cur][k];
-          sc.curR[k] = sc.mend[cur][k];
+          const uint32_t st = x.mstart[k], en = x.mend[k];
+          work_part += en - st;
+          sc.curL[k] = st;
+          sc.curR[k] = en;
           const uint32_t NL = sc.dNL[k];
           const int64_t SL = sc.dSL[k];
           const uint64_t QL = sc.dQL[k];
-          sc.mstart[nxt][2 * r] = sc.mstart[cur][k];
-          sc.mN[nxt][2 * r] = NL;
-          sc.mS[nxt][2 * r] = SL;
-          sc.mQ[nxt][2 * r] = QL;
-          sc.mend[nxt][2 * r + 1] = sc.mend[cur][k];
-          sc.mN[nxt][2 * r + 1] = N - NL;
-          sc.mS[nxt][2 * r + 1] = S - SL;
-          sc.mQ[nxt][2 * r + 1] = sc.mQ[cur][k] - QL;
+          X.mstart[2 * r] = st;
+          X.mN[2 * r] = NL;
+          X.mS[2 * r] = SL;
+          X.mQ[2 * r] = QL;
+          X.mend[2 * r + 1] = en;
+          X.mN[2 * r + 1] = N - NL;
+          X.mS[2 * r + 1] = S - SL;
+          X.mQ[2 * r + 1] = x.mQ[k] - QL;
         } else {
           a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
         }
@@ -540,45 +714,66 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       next_id = (uint32_t)T.capacity;
       break;
     }
-    // (e) partition the entries of split nodes into their children's segments
-    for (uint32_t p = tid; p < n_inbag; p += BLOCK) {
-      const int32_t k = sc.slot[cur][p];
-      if (k >= 0 && sc.status[k] == kSplit) {
-        const uint64_t e = sc.buf[cur][p];
-        const uint32_t code = a.codes[(size_t)entry_row(e) * a.C + sc.dcol[k]];
-        uint32_t dst;
-        int32_t child;
-        if (code <= sc.dbin[k]) {
-          dst = atomicAdd(&sc.curL[k], 1u);
-          child = (int32_t)(2 * sc.rank[k]);
-        } else {
-          dst = atomicSub(&sc.curR[k], 1u) - 1u;
-          child = (int32_t)(2 * sc.rank[k] + 1);
+    // (f) partition the entries of split nodes into their children's segments;
+    // the lanes of a wave that send rows of one node to one side share a
+    // single cursor atomic, and take consecutive slots in lane order
+    for (uint32_t b0 = 0; b0 < n_inbag; b0 += BLOCK) {
+      const uint32_t p = b0 + tid;
+      const int32_t k = p < n_inbag ? C.slot[p] : -1;
+      const bool mv = k >= 0 && sc.status[k] == kSplit;
+      uint64_t e = 0;
+      uint32_t side = 0;
+      if (mv) {
+        e = C.buf[p];
+        side = a.codes[(size_t)entry_row(e) * a.C + sc.dcol[k]] <= sc.dbin[k] ? 0u : 1u;
+      } else if (p < n_inbag) {
+        X.slot[p] = -1;
+      }
+      const int32_t key = mv ? (int32_t)(2 * k + side) : -1;
+      const uint64_t below_mask = (1ull << lane) - 1ull;
+      uint64_t todo = __ballot(mv);
+      uint32_t my_base = 0, my_rank = 0;
+      int my_leader = 0;
+      while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t peers = __ballot(key == lkey) & todo;
+        todo &= ~peers;
+        if (key == lkey) {
+          my_leader = leader;
+          my_rank = (uint32_t)__popcll(peers & below_mask);
         }
-        sc.buf[nxt][dst] = e;
-        sc.slot[nxt][dst] = child;
-      } else {
-        sc.slot[nxt][p] = -1;
+        if (lane == leader) {
+          const uint32_t cnt = (uint32_t)__popcll(peers);
+          const uint32_t kk = (uint32_t)lkey >> 1;
+          my_base = (lkey & 1) ? atomicSub(&sc.curR[kk], cnt) - cnt : atomicAdd(&sc.curL[kk], cnt);
+        }
+      }
+      const uint32_t base = (uint32_t)__shfl((int)my_base, my_leader, kWave);
+      if (mv) {
+        const uint32_t dst = base + my_rank;
+        X.buf[dst] = e;
+        X.slot[dst] = (int32_t)(2 * sc.rank[k] + side);
       }
     }
     __syncthreads();
-    // (f) the boundary between each pair of children
+    // (g) the boundary between each pair of children
     for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
       if (sc.status[k] == kSplit) {
         const uint32_t r = sc.rank[k];
-        sc.mend[nxt][2 * r] = sc.curL[k];
-        sc.mstart[nxt][2 * r + 1] = sc.curL[k];
+        X.mend[2 * r] = sc.curL[k];
+        X.mstart[2 * r + 1] = sc.curL[k];
       }
     }
     __syncthreads();
     level_lo = next_id;
     level_cnt = 2 * n_split;
     next_id += 2 * n_split;
-    cur = nxt;
+    cur ^= 1;
   }
-  work_rows = block_sum<BLOCK, uint64_t>(work_rows, s_red);
-  work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, s_red);
-  work_part = block_sum<BLOCK, uint64_t>(work_part, s_red);
+  work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
+  work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, sh.red);
+  work_part = block_sum<BLOCK, uint64_t>(work_part, sh.red);
   if (tid == 0) {
     a.n_nodes[task_index] = (int32_t)next_id;
     int64_t* wk = a.work + 4 * (int64_t)task_index;
@@ -587,26 +782,23 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     wk[2] = (int64_t)work_part;
     wk[3] = (int64_t)levels;
   }
+  (void)wid;
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_grow(GrowArgs a) {
-  constexpr int NW = BLOCK / kWave;
-  __shared__ WaveLds wl[NW];
-  __shared__ uint32_t s_tmp[NW + 1];
-  __shared__ uint64_t s_red[NW];
-  __shared__ uint32_t s_cnt[2];
-  __shared__ uint32_t s_task;
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ Shared sh;
   Scratch sc;
   carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max);
   for (;;) {
-    if (threadIdx.x == 0) s_task = atomicAdd(a.queue, 1u);
+    if (threadIdx.x == 0) sh.task = atomicAdd(a.queue, 1u);
     __syncthreads();
-    const uint32_t t = s_task;
+    const uint32_t t = sh.task;
     __syncthreads();
     if (t >= (uint32_t)a.n_tasks) return;
     const TreeTask T = a.tasks[t];
-    grow_tree<BLOCK>(a, T, (int32_t)t, sc, wl, s_tmp, s_red, s_cnt);
+    grow_tree<BLOCK>(a, T, (int32_t)t, sc, lds, sh);
     __syncthreads();
   }
 }
@@ -643,6 +835,41 @@ __global__ void k_set_i32(int32_t* p, int32_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Dynamic LDS of the grow kernel: the per-wave histograms, or the histograms of
+// a huge node's candidate columns, or the candidate-draw rows, whichever is
+// largest (the three are used in different phases of a level).
+struct Layout {
+  uint32_t union_bytes;
+  int32_t bstride;
+  int32_t huge_cols;
+};
+
+Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
+  Layout L;
+  L.bstride = (std::max(cfg.bins_max, 1) + 63) / 64 * 64;
+  const size_t waves = (size_t)(cfg.block / kWave) * sizeof(WaveHist);
+  const size_t draw = (size_t)std::min(cfg.block, 256) * (size_t)C;
+  const size_t col_bytes = (size_t)L.bstride * (4 + 8 + 8);
+  size_t huge = 0;
+  if (cfg.n_cap > cfg.huge_min) {
+    const size_t cap = std::max<size_t>(waves, 96 * 1024);
+    const size_t cols = std::max<size_t>(1, std::min<size_t>((size_t)mtry_max, cap / col_bytes));
+    huge = cols * col_bytes;
+  }
+  L.union_bytes = (uint32_t)std::max(std::max(waves, huge), draw);
+  L.huge_cols = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)mtry_max, L.union_bytes / col_bytes));
+  return L;
+}
+
+template <int BLOCK>
+int occupancy(uint32_t lds) {
+  int nb = 0;
+  AIWC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_grow<BLOCK>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grow<BLOCK>, BLOCK, lds));
+  return nb;
+}
+
 }  // namespace
 
 void launch_init(uint32_t* d_status, uint32_t* d_queue, hipStream_t s) {
@@ -668,21 +895,17 @@ void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d
   AIWC_HIP(hipGetLastError());
 }
 
-template <int BLOCK>
-static int occupancy() {
-  int nb = 0;
-  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grow<BLOCK>, BLOCK, 0));
-  return std::max(nb, 1);
-}
-
-int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks) {
+int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C) {
+  const uint32_t lds = grow_layout(cfg, mtry_max, C).union_bytes;
+  if (lds > device_info().lds_per_block) fail(AIWC_RF_EINVAL, "grow kernel LDS exceeds the device limit");
   int per_cu = 1;
   switch (cfg.block) {
-    case 256: per_cu = occupancy<256>(); break;
-    case 512: per_cu = occupancy<512>(); break;
-    case 1024: per_cu = occupancy<1024>(); break;
+    case 256: per_cu = occupancy<256>(lds); break;
+    case 512: per_cu = occupancy<512>(lds); break;
+    case 1024: per_cu = occupancy<1024>(lds); break;
     default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
   }
+  if (per_cu < 1) fail(AIWC_RF_ENOMEM, "grow kernel does not fit the device (LDS or registers)");
   if (cfg.wg_per_cu > 0) per_cu = std::min(per_cu, cfg.wg_per_cu);
   const int64_t slots = (int64_t)device_info().cus * per_cu;
   return (int)std::max<int64_t>(1, std::min<int64_t>(slots, n_tasks));
@@ -709,11 +932,16 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const i
   a.scratch = scratch;
   a.n_cap = n_cap;
   a.mtry_max = mtry_max;
+  a.huge_min = cfg.huge_min;
   a.scratch_stride = grow_scratch_bytes(n_cap, mtry_max);
+  const Layout L = grow_layout(cfg, mtry_max, C);
+  a.union_bytes = L.union_bytes;
+  a.bstride = L.bstride;
+  a.huge_cols = L.huge_cols;
   switch (cfg.block) {
-    case 256: k_grow<256><<<grid, 256, 0, s>>>(a); break;
-    case 512: k_grow<512><<<grid, 512, 0, s>>>(a); break;
-    case 1024: k_grow<1024><<<grid, 1024, 0, s>>>(a); break;
+    case 256: k_grow<256><<<grid, 256, a.union_bytes, s>>>(a); break;
+    case 512: k_grow<512><<<grid, 512, a.union_bytes, s>>>(a); break;
+    case 1024: k_grow<1024><<<grid, 1024, a.union_bytes, s>>>(a); break;
     default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
   }
   AIWC_HIP(hipGetLastError());

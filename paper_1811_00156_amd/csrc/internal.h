@@ -144,15 +144,18 @@ void launch_bin_encode(const float* X, const int32_t* dev, int64_t n, int32_t p,
 
 // fit.hip
 struct GrowConfig {
-  int block = 512;      // threads per workgroup
-  int wg_per_cu = 0;    // 0 = as many as occupancy allows
+  int block = 512;       // threads per workgroup
+  int wg_per_cu = 0;     // 0 = as many as occupancy allows
+  int huge_min = 4096;   // nodes with more in-bag rows use the workgroup-wide histogram
+  int bins_max = 256;    // largest bin count of any column
+  int64_t n_cap = 0;     // largest training set of any tree
 };
 void launch_init(uint32_t* d_status, uint32_t* d_queue, hipStream_t s);  // either may be null
 void launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
                     int64_t* y_fp, uint32_t* d_status, hipStream_t s);
 size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
-int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks);
+int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
 void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
                  uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint32_t* d_queue,
