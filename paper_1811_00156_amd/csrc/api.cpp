@@ -66,9 +66,15 @@ int32_t status_to_code(uint32_t st, std::string& msg) {
   return AIWC_RF_OK;
 }
 
-GrowConfig grow_config(int64_t n_cap, const std::vector<int32_t>& n_bins) {
+GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t>& n_bins) {
   GrowConfig cfg;
-  cfg.block = n_cap > 16384 ? 1024 : 512;
+  // large training sets: the biggest workgroups (huge-node histograms span all
+  // waves); small ones: 512 threads per tree while trees are few, 256 once there
+  // are enough trees to fill four workgroups per CU
+  if (n_cap > 16384)
+    cfg.block = 1024;
+  else
+    cfg.block = n_tasks >= 4LL * device_info().cus ? 256 : 512;
   cfg.n_cap = n_cap;
   cfg.bins_max = 1;
   for (int32_t b : n_bins) cfg.bins_max = std::max(cfg.bins_max, b);
@@ -317,7 +323,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     DevBuf<int64_t> y_fp((size_t)n, s);
     DevBuf<uint32_t> queue(1, s);
 
-    const GrowConfig cfg = grow_config(n_cap, binner->n_bins);
+    const GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
     const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
     const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
 

@@ -33,8 +33,11 @@
 namespace aiwc {
 namespace {
 
-constexpr uint8_t kLeaf = 0, kTiny = 1, kBig = 2, kHuge = 3, kSplit = 4;
-constexpr uint32_t kTinyMax = 16;  // rows per node handled by the all-pairs lane method
+constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kHuge = 3, kSplit = 4;
+// Nodes with at most kSegMax in-bag rows are searched with their rows in a
+// lane segment of width 4, 8, 16 or 32 (the smallest that holds them).
+constexpr uint32_t kSegMax = 32;
+constexpr int kSegClasses = 4;
 constexpr int kMaxBins = 256;
 
 struct Rec {
@@ -71,7 +74,7 @@ struct Scratch {
   uint32_t* rank;
   uint32_t* curL;
   uint32_t* curR;
-  uint32_t* tiny;
+  uint32_t* seg[kSegClasses];  // small nodes by segment width 4 << class
   uint32_t* big;
   uint32_t* huge;
   Rec* recs;  // large node j's candidate i at j * mtry + i
@@ -85,8 +88,8 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
     return base + o;
   };
   const size_t n = (size_t)n_cap;
-  // large and huge nodes hold more than kTinyMax rows each
-  const size_t n_large = n / (kTinyMax + 1) + 1;
+  // large and huge nodes hold more than kSegMax rows each
+  const size_t n_large = n / (kSegMax + 1) + 1;
   s->cnt = reinterpret_cast<uint32_t*>(take(4 * n));
   Level2* lv[2] = {&s->L0, &s->L1};
   for (int b = 0; b < 2; ++b) {
@@ -108,7 +111,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->tiny = reinterpret_cast<uint32_t*>(take(4 * n));
+  for (int c = 0; c < kSegClasses; ++c) s->seg[c] = reinterpret_cast<uint32_t*>(take(4 * (n / (1 + (c ? (2u << c) : 0)) + 1)));
   s->big = reinterpret_cast<uint32_t*>(take(4 * n_large));
   s->huge = reinterpret_cast<uint32_t*>(take(4 * n_large));
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
@@ -220,36 +223,6 @@ __device__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t 
   for (uint64_t m = m3; m; m &= m - 1) out[i++] = (uint8_t)(192 + __builtin_ctzll(m));
 }
 
-// Best split of one column for a node of at most L rows held in registers,
-// cw[r] = code << 24 | weight and wy[r] = weight * y_fp: for every row a, the
-// left side is every row whose code is <= code[a].
-template <int L>
-__device__ __forceinline__ void tiny_column(const uint32_t (&cw)[kTinyMax], const int64_t (&wy)[kTinyMax], uint32_t len,
-                                            uint32_t N, int64_t S, uint32_t col, double& best, uint32_t& best_cb) {
-#pragma unroll
-  for (int a = 0; a < L; ++a) {
-    if ((uint32_t)a < len) {
-      const uint32_t ca = cw[a] >> 24;
-      uint32_t NL = 0;
-      int64_t SL = 0;
-#pragma unroll
-      for (int b = 0; b < L; ++b) {
-        const bool in = (uint32_t)b < len && (cw[b] >> 24) <= ca;
-        NL += in ? (cw[b] & 0xFFFFFFu) : 0u;
-        SL += in ? wy[b] : 0;
-      }
-      if (NL < N) {
-        const double s = split_score(SL, NL, S - SL, N - NL);
-        const uint32_t cb = (col << 8) | ca;
-        if (s > best || (s == best && cb < best_cb)) {
-          best = s;
-          best_cb = cb;
-        }
-      }
-    }
-  }
-}
-
 struct Ctx {
   const GrowArgs* a;
   const TreeTask* T;
@@ -262,89 +235,96 @@ struct Ctx {
   const uint64_t* mQ;
 };
 
-// Tiny nodes: a wave takes P = 64 / G nodes (G = min(mtry, 64) lanes each);
-// lane (g, i) evaluates candidate columns i, i + G, ... of node g, then the
-// group's first lane combines the group (max score, then lowest (column, bin))
-// and decides the node.  Each lane keeps its node's row ids in its own column
-// of the wave's LDS area and the (code, weight, weight * y) of the column being
-// evaluated in registers.
-__device__ void tiny_task(const Ctx& x, uint32_t t, uint32_t n_tiny, WaveHist& wl) {
+// Small nodes (at most kSegMax rows): a wave takes P = 64 / W nodes whose rows
+// fit a segment of W lanes, one row per lane.  For each candidate position i
+// (node k's i-th column, ascending) every lane takes the split at its own
+// row's code: the left sums come from the W rows of its segment staged in
+// LDS, the segment keeps the best (max score, then lowest bin), and across
+// columns a strictly greater score is needed, so ties keep the lowest column.
+// The segment's first lane then decides the node; the children's sums come
+// from one more segment reduction over the winning column.
+template <int W>
+__device__ void small_task(const Ctx& x, const uint32_t* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
   const int lane = (int)lane_id();
-  const int G = mtry < kWave ? mtry : kWave;
-  const int P = kWave / G;
-  const int g = lane / G, i0 = lane % G;
+  constexpr int P = kWave / W;
+  const int g = lane / W, r = lane % W, sbase = g * W;
   const uint32_t idx = t * (uint32_t)P + (uint32_t)g;
-  const bool active = g < P && idx < n_tiny;
-  const uint32_t k = active ? x.sc.tiny[idx] : 0u;
-  const uint32_t start = active ? x.mstart[k] : 0u;
-  const uint32_t len = active ? x.mend[k] - start : 0u;
-  const uint32_t N = active ? x.mN[k] : 0u;
-  const int64_t S = active ? x.mS[k] : 0;
+  const bool node_ok = idx < n_list;
+  const uint32_t k = node_ok ? list[idx] : 0u;
+  const uint32_t start = node_ok ? x.mstart[k] : 0u;
+  const uint32_t len = node_ok ? x.mend[k] - start : 0u;
+  const uint32_t N = node_ok ? x.mN[k] : 0u;
+  const int64_t S = node_ok ? x.mS[k] : 0;
+  const bool valid = (uint32_t)r < len;
+  const uint64_t e = valid ? x.buf[start + r] : 0ull;
+  const uint32_t row = entry_row(e);
+  const uint32_t w = valid ? entry_w(e) : 0u;
+  const int64_t y = entry_y(e);
+  const int64_t wy = (int64_t)w * y;
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
-  uint32_t* rows = reinterpret_cast<uint32_t*>(area);              // [kTinyMax][64]
-  double* s_score = reinterpret_cast<double*>(area + 4096);        // [64]
-  uint32_t* s_cb = reinterpret_cast<uint32_t*>(area + 4096 + 512);  // [64]
+  int64_t* s_wy = reinterpret_cast<int64_t*>(area);        // [64]
+  uint32_t* s_w = reinterpret_cast<uint32_t*>(area + 512);  // [64]
+  uint8_t* s_codes = area + 1024;                           // [64 columns][64 lanes]
+  s_wy[lane] = wy;
+  s_w[lane] = w;
+  const uint8_t* rowp = a.codes + (size_t)row * a.C;
+  const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
 
-  uint32_t cw[kTinyMax];
-  int64_t wy[kTinyMax];
-#pragma unroll
-  for (int r = 0; r < (int)kTinyMax; ++r) {
-    const uint64_t e = (uint32_t)r < len ? x.buf[start + r] : 0ull;
-    const uint32_t w = (uint32_t)r < len ? entry_w(e) : 0u;
-    rows[r * kWave + lane] = entry_row(e);
-    cw[r] = w;
-    wy[r] = (int64_t)w * entry_y(e);
-  }
   double best = -1.0;
   uint32_t best_cb = 0xFFFFFFFFu;
-  // one unrolled loop length per wave; shorter nodes are predicated
-  uint32_t lmax = len;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, d, kWave));
-  lmax = rfl(lmax);
-  for (int i = i0; active && i < mtry; i += G) {
-    const uint32_t c = x.sc.cand[(size_t)k * mtry + i];
-#pragma unroll
-    for (int r = 0; r < (int)kTinyMax; ++r) {
-      const uint32_t code = (uint32_t)r < len ? a.codes[(size_t)rows[r * kWave + lane] * a.C + c] : 0u;
-      cw[r] = (cw[r] & 0xFFFFFFu) | (code << 24);
-    }
-    if (lmax <= 4)
-      tiny_column<4>(cw, wy, len, N, S, c, best, best_cb);
-    else if (lmax <= 8)
-      tiny_column<8>(cw, wy, len, N, S, c, best, best_cb);
-    else
-      tiny_column<16>(cw, wy, len, N, S, c, best, best_cb);
-  }
-  // combine each group in LDS
-  s_score[lane] = best;
-  s_cb[lane] = best_cb;
-  wave_lds_sync();
-  if (active && i0 == 0) {
-    for (int j = 1; j < G; ++j) {
-      const double s = s_score[lane + j];
-      const uint32_t cb = s_cb[lane + j];
-      if (s > best || (s == best && cb < best_cb)) {
-        best = s;
-        best_cb = cb;
-      }
-    }
-    if (best >= 0.0 && best - parent_score(S, N) > 0.0) {
-      const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+  for (int i0 = 0; i0 < mtry; i0 += kWave) {
+    const int nc = min(kWave, mtry - i0);
+    // gather the row's codes in every candidate column of this chunk at once
+#pragma unroll 8
+    for (int i = 0; i < nc; ++i) s_codes[i * kWave + lane] = valid ? rowp[node_ok ? cand[i0 + i] : 0] : 0;
+    wave_lds_sync();
+    for (int i = i0; i < i0 + nc; ++i) {
+      const uint32_t c = node_ok ? cand[i] : 0u;
+      const uint8_t* col_codes = s_codes + (i - i0) * kWave;
+      const uint32_t code = col_codes[lane];
       uint32_t NL = 0;
       int64_t SL = 0;
-      uint64_t QL = 0;
-      for (uint32_t r = 0; r < len; ++r) {
-        const uint64_t e = x.buf[start + r];
-        if (a.codes[(size_t)entry_row(e) * a.C + col] <= bin) {
-          const int64_t ww = (int64_t)entry_w(e), y = entry_y(e);
-          NL += (uint32_t)ww;
-          SL += ww * y;
-          QL += (uint64_t)(ww * y * y);
+#pragma unroll 4
+      for (int b = 0; b < W; ++b) {
+        const bool in = col_codes[sbase + b] <= code;
+        NL += in ? s_w[sbase + b] : 0u;
+        SL += in ? s_wy[sbase + b] : 0;
+      }
+      double sc = -1.0;
+      if (valid && NL < N) sc = split_score(SL, NL, S - SL, N - NL);
+      uint32_t key = code;
+#pragma unroll
+      for (int d = W / 2; d >= 1; d >>= 1) {
+        const double os = __shfl_xor(sc, d, W);
+        const uint32_t ok = (uint32_t)__shfl_xor((int)key, d, W);
+        if (os > sc || (os == sc && ok < key)) {
+          sc = os;
+          key = ok;
         }
       }
+      if (sc > best) {
+        best = sc;
+        best_cb = (c << 8) | key;
+      }
+    }
+    wave_lds_sync();
+  }
+  const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
+  const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+  const bool left = split && valid && rowp[col] <= bin;
+  uint32_t NL = left ? w : 0u;
+  int64_t SL = left ? wy : 0;
+  uint64_t QL = left ? (uint64_t)(wy * y) : 0ull;
+#pragma unroll
+  for (int d = W / 2; d >= 1; d >>= 1) {
+    NL += (uint32_t)__shfl_xor((int)NL, d, W);
+    SL += __shfl_xor(SL, d, W);
+    QL += __shfl_xor(QL, d, W);
+  }
+  if (node_ok && r == 0) {
+    if (split) {
       x.sc.dcol[k] = (uint8_t)col;
       x.sc.dbin[k] = (uint8_t)bin;
       x.sc.dNL[k] = NL;
@@ -385,10 +365,13 @@ __device__ __forceinline__ ArgMax scan_column(const uint32_t* hN, const uint64_t
   oSL = 0;
   oQL = 0;
   for (int b = b0; b < b1; ++b) {
-    NL += hN[b];
+    const uint32_t hn = hN[b];
+    // an empty bin repeats the previous split, which already won any tie
+    if (hn == 0) continue;
+    NL += hn;
     SL += (int64_t)hS[b];
     QL += hQ[b];
-    if (b <= B - 2 && NL > 0 && NL < N) {
+    if (b <= B - 2 && NL < N) {
       const double s = split_score(SL, NL, S - SL, N - NL);
       if (s > lbest) {
         lbest = s;
@@ -420,15 +403,26 @@ __device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
     L.hQ[b] = 0;
   }
   wave_lds_sync();
-  for (uint32_t p = start + lane; p < end; p += kWave) {
-    const uint64_t e = x.buf[p];
-    const uint32_t w = entry_w(e);
-    const int64_t y = entry_y(e);
-    const uint32_t code = a.codes[(size_t)entry_row(e) * a.C + c];
-    const int64_t wy = (int64_t)w * y;
-    atomicAdd(&L.hN[code], w);
-    atomicAdd((unsigned long long*)&L.hS[code], (unsigned long long)wy);
-    atomicAdd((unsigned long long*)&L.hQ[code], (unsigned long long)(wy * y));
+  // four rows per lane in flight: entries, then codes, then the atomics
+  constexpr int U = 4;
+  for (uint32_t p0 = start + lane; p0 < end; p0 += U * kWave) {
+    uint64_t e[U];
+    uint32_t code[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) e[u] = p0 + u * kWave < end ? x.buf[p0 + u * kWave] : 0ull;
+#pragma unroll
+    for (int u = 0; u < U; ++u) code[u] = p0 + u * kWave < end ? a.codes[(size_t)entry_row(e[u]) * a.C + c] : 0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (p0 + u * kWave < end) {
+        const uint32_t w = entry_w(e[u]);
+        const int64_t y = entry_y(e[u]);
+        const int64_t wy = (int64_t)w * y;
+        atomicAdd(&L.hN[code[u]], w);
+        atomicAdd((unsigned long long*)&L.hS[code[u]], (unsigned long long)wy);
+        atomicAdd((unsigned long long*)&L.hQ[code[u]], (unsigned long long)(wy * y));
+      }
+    }
   }
   wave_lds_sync();
   uint32_t NL;
@@ -477,7 +471,7 @@ __device__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int 
 struct Shared {
   uint32_t tmp[17];
   uint64_t red[16];
-  uint32_t cnt[3];
+  uint32_t cnt[3 + kSegClasses];  // [1] large, [2] huge, [3..] small nodes per segment width
   uint32_t task;
   uint8_t cand[256];
   Rec recs[256];
@@ -515,11 +509,20 @@ __device__ void huge_node(const Ctx& x, uint32_t k, uint8_t* lds, Shared& sh) {
       const int64_t wy = (int64_t)w * y;
       const uint64_t wyy = (uint64_t)(wy * y);
       const uint8_t* rp = a.codes + (size_t)entry_row(e) * a.C;
-      for (int i = 0; i < nc; ++i) {
-        const int h = i * bs + rp[sh.cand[c0 + i]];
-        atomicAdd(&hN[h], w);
-        atomicAdd((unsigned long long*)&hS[h], (unsigned long long)wy);
-        atomicAdd((unsigned long long*)&hQ[h], (unsigned long long)wyy);
+      // the row's codes in eight candidate columns are fetched together
+      for (int i0 = 0; i0 < nc; i0 += 8) {
+        uint32_t cd[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cd[u] = i0 + u < nc ? rp[sh.cand[c0 + i0 + u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (i0 + u < nc) {
+            const int h = (i0 + u) * bs + (int)cd[u];
+            atomicAdd(&hN[h], w);
+            atomicAdd((unsigned long long*)&hS[h], (unsigned long long)wy);
+            atomicAdd((unsigned long long*)&hQ[h], (unsigned long long)wyy);
+          }
+        }
       }
     }
     __syncthreads();
@@ -612,11 +615,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
     const Ctx x{&a, &T, sc, C.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
     // (a) leaf rules, candidate draws, tiers
-    if (tid == 0) {
-      sh.cnt[0] = 0;
-      sh.cnt[1] = 0;
-      sh.cnt[2] = 0;
-    }
+    if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
     __syncthreads();
     if (tid < n_draw) {
       for (uint32_t k = tid; k < level_cnt; k += n_draw) {
@@ -632,9 +631,11 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
                         sc.cand + (size_t)k * mtry);
         work_rows += len;
         ++work_nodes;
-        if (len <= kTinyMax) {
-          sc.status[k] = kTiny;
-          sc.tiny[atomicAdd(&sh.cnt[0], 1u)] = k;
+        if (len <= kSegMax) {
+          const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : 3;
+          sc.status[k] = kSmall;
+          uint32_t* list = cls == 0 ? sc.seg[0] : cls == 1 ? sc.seg[1] : cls == 2 ? sc.seg[2] : sc.seg[3];
+          list[atomicAdd(&sh.cnt[3 + cls], 1u)] = k;
         } else if ((int32_t)len <= a.huge_min) {
           sc.status[k] = kBig;
           sc.big[atomicAdd(&sh.cnt[1], 1u)] = k;
@@ -645,21 +646,30 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       }
     }
     __syncthreads();
-    const uint32_t n_tiny = sh.cnt[0], n_big = sh.cnt[1], n_huge = sh.cnt[2];
+    const uint32_t n_big = sh.cnt[1], n_huge = sh.cnt[2];
     // (b) huge nodes, one after another, with the whole workgroup
     for (uint32_t h = 0; h < n_huge; ++h) huge_node<BLOCK>(x, sc.huge[h], lds, sh);
-    // (c) large-node columns and tiny-node groups, one wave each
+    // (c) large-node columns and small-node segments, one wave each
     {
-      const int G = mtry < kWave ? mtry : kWave;
-      const uint32_t P = (uint32_t)(kWave / G);
       const uint32_t n_big_tasks = n_big * (uint32_t)mtry;
-      const uint32_t n_tiny_tasks = (n_tiny + P - 1) / P;
+      uint32_t first[kSegClasses + 1];
+      first[0] = n_big_tasks;
+      for (int c = 0; c < kSegClasses; ++c) {
+        const uint32_t per_wave = (uint32_t)(kWave >> (2 + c));
+        first[c + 1] = first[c] + (sh.cnt[3 + c] + per_wave - 1) / per_wave;
+      }
       WaveHist& wl = reinterpret_cast<WaveHist*>(lds)[wid];
-      for (uint32_t t = wid; t < n_big_tasks + n_tiny_tasks; t += NW) {
+      for (uint32_t t = wid; t < first[kSegClasses]; t += NW) {
         if (t < n_big_tasks)
           big_task(x, t / mtry, (int)(t % mtry), wl);
+        else if (t < first[1])
+          small_task<4>(x, sc.seg[0], t - first[0], sh.cnt[3], wl);
+        else if (t < first[2])
+          small_task<8>(x, sc.seg[1], t - first[1], sh.cnt[4], wl);
+        else if (t < first[3])
+          small_task<16>(x, sc.seg[2], t - first[2], sh.cnt[5], wl);
         else
-          tiny_task(x, t - n_big_tasks, n_tiny, wl);
+          small_task<32>(x, sc.seg[3], t - first[3], sh.cnt[6], wl);
       }
     }
     __syncthreads();
@@ -785,8 +795,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
   (void)wid;
 }
 
+// At most 128 VGPRs (four waves per SIMD): the persistent kernel is bound by
+// latency, so resident waves matter more than the few registers it spills.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_grow(GrowArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_grow(GrowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ Shared sh;
   Scratch sc;

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/aiwc_rf.h"
+#include "aiwc_rf.h"
 
 namespace aiwc {
 

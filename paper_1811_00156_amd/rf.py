@@ -22,6 +22,10 @@ FIT_FUSED, FIT_PLAIN, FIT_ASYNC = 0, 1, 2
 LEAF = 255
 MAX_ROWS = 1 << 18
 
+# torch first: the library must bind to the HIP runtime torch already loaded, so
+# that device pointers and stream handles mean the same thing on both sides.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
 
