@@ -63,6 +63,26 @@ def grow_bytes(work, mtry, total_nodes):
     return searched_rows * (8 + mtry) + part_rows * 17 + total_nodes * 12
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the rocprofv3 counter runs summarised in
+    profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel_key)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec["kernel_sha256_16"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def run_cpu_baseline(wl, ds, sample_trees, steps_cap_s=30.0):
     from oracle import oracle as O
 
@@ -159,7 +179,7 @@ def bench_forest(args, wl_name):
         "tree_stats": {"total_nodes": int(total_nodes), "searched_rows": int(work[0]), "searched_nodes": int(work[1]),
                        "partitioned_rows": int(work[2]), "max_levels": int(work[3])},
         "roofline": {"kernel": "k_grow", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"k_grow@{wl_name}"),
                      "algorithmic_bytes_per_launch": int(gbytes), "avg_launch_ms": g_ms},
     }
     if not args.no_cpu_baseline:
@@ -305,12 +325,35 @@ def bench_serve(args):
     }
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of known size: the reference that scales
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    gbs = 2 * nbytes / (ms / 1000.0) / 1e9
+    return {"metric": "device copy GB/s (counter calibration)", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"copy: {nbytes} bytes read + {nbytes} bytes written per step"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy"])
     ap.add_argument("--requests", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -323,7 +366,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
-    if args.workload == "c4":
+    if args.workload == "copy":
+        res = bench_copy(args)
+    elif args.workload == "c4":
         res = bench_grid(args)
     elif args.workload == "c5":
         res = bench_serve(args)
