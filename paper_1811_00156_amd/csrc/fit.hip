@@ -11,8 +11,9 @@
 //      (min.node.size, purity) and draws the node's mtry candidate columns; the
 //      split search over every (candidate column, bin) is then tiered by the
 //      node's number of in-bag rows:
-//        - tiny  (<= 16 rows): one lane per (node, column), rows in registers,
-//          the left sums of every present code found by an all-pairs pass;
+//        - small (<= 64 rows): one row per lane in a segment of 4..64 lanes,
+//          every candidate column's codes gathered at once, the left sums of
+//          each lane's split found from the segment's rows staged in LDS;
 //        - large (<= huge limit): one wave per (node, column), LDS histogram of
 //          (N, S, Q) per bin and a wave prefix scan over bins;
 //        - huge: the whole workgroup builds the LDS histograms of all candidate
@@ -35,10 +36,20 @@ namespace {
 
 constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kHuge = 3, kSplit = 4;
 // Nodes with at most kSegMax in-bag rows are searched with their rows in a
-// lane segment of width 4, 8, 16 or 32 (the smallest that holds them).
-constexpr uint32_t kSegMax = 32;
-constexpr int kSegClasses = 4;
+// lane segment of width 4, 8, 16, 32 or 64 (the smallest that holds them).
+constexpr uint32_t kSegMax = 64;
+constexpr int kSegClasses = 5;
 constexpr int kMaxBins = 256;
+
+// A searched node as the split-search tasks see it (filled when the node is
+// classified, so a task needs one dependent load to find its rows).
+struct NodeDesc {
+  uint32_t k;      // index of the node within its level
+  uint32_t start;  // first entry of its segment
+  uint32_t len;    // in-bag rows
+  uint32_t N;      // bootstrap weight
+  int64_t S;       // sum of weight * y_fp
+};
 
 struct Rec {
   double score;
@@ -74,8 +85,8 @@ struct Scratch {
   uint32_t* rank;
   uint32_t* curL;
   uint32_t* curR;
-  uint32_t* seg[kSegClasses];  // small nodes by segment width 4 << class
-  uint32_t* big;
+  NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
+  NodeDesc* big;
   uint32_t* huge;
   Rec* recs;  // large node j's candidate i at j * mtry + i
 };
@@ -111,15 +122,17 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
-  for (int c = 0; c < kSegClasses; ++c) s->seg[c] = reinterpret_cast<uint32_t*>(take(4 * (n / (1 + (c ? (2u << c) : 0)) + 1)));
-  s->big = reinterpret_cast<uint32_t*>(take(4 * n_large));
+  // class c holds nodes of more than 2 << c rows (c >= 1)
+  for (int c = 0; c < kSegClasses; ++c)
+    s->seg[c] = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * (n / (1 + (c ? (2u << c) : 0)) + 1)));
+  s->big = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
   s->huge = reinterpret_cast<uint32_t*>(take(4 * n_large));
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   return off;
 }
 
-// Per-wave LDS: one histogram of (N, S, Q) over at most 256 bins.  The tiny
-// method reuses it for the per-lane results.
+// Per-wave LDS: one histogram of (N, S, Q) over at most 256 bins.  The small
+// node method reuses it for the segment's staged rows and codes.
 struct WaveHist {
   uint32_t hN[kMaxBins];
   uint64_t hS[kMaxBins];
@@ -244,7 +257,7 @@ struct Ctx {
 // The segment's first lane then decides the node; the children's sums come
 // from one more segment reduction over the winning column.
 template <int W>
-__device__ void small_task(const Ctx& x, const uint32_t* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
+__device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
   const int lane = (int)lane_id();
@@ -252,11 +265,10 @@ __device__ void small_task(const Ctx& x, const uint32_t* list, uint32_t t, uint3
   const int g = lane / W, r = lane % W, sbase = g * W;
   const uint32_t idx = t * (uint32_t)P + (uint32_t)g;
   const bool node_ok = idx < n_list;
-  const uint32_t k = node_ok ? list[idx] : 0u;
-  const uint32_t start = node_ok ? x.mstart[k] : 0u;
-  const uint32_t len = node_ok ? x.mend[k] - start : 0u;
-  const uint32_t N = node_ok ? x.mN[k] : 0u;
-  const int64_t S = node_ok ? x.mS[k] : 0;
+  NodeDesc d{0u, 0u, 0u, 0u, 0};
+  if (node_ok) d = list[idx];
+  const uint32_t k = d.k, start = d.start, len = d.len, N = d.N;
+  const int64_t S = d.S;
   const bool valid = (uint32_t)r < len;
   const uint64_t e = valid ? x.buf[start + r] : 0ull;
   const uint32_t row = entry_row(e);
@@ -338,6 +350,107 @@ __device__ void small_task(const Ctx& x, const uint32_t* list, uint32_t t, uint3
   wave_lds_sync();
 }
 
+// Nodes of 33..64 rows: one node per wave, one row per lane.  Per candidate
+// column the rows' weights and sums are added into LDS bins of the codes that
+// occur, the occurring codes are ranked through a 256-bit presence mask, and a
+// wave prefix scan over the ranked codes gives the left sums of every split
+// (cost independent of the bin count and of the number of rows).
+__device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
+  const GrowArgs& a = *x.a;
+  const int mtry = x.T->mtry;
+  const int lane = (int)lane_id();
+  if (t >= n_list) return;
+  const NodeDesc d = list[t];
+  const uint32_t k = rfl(d.k), start = rfl(d.start), len = rfl(d.len), N = rfl(d.N);
+  const int64_t S = d.S;
+  const bool valid = (uint32_t)lane < len;
+  const uint64_t e = valid ? x.buf[start + lane] : 0ull;
+  const uint32_t w = valid ? entry_w(e) : 0u;
+  const int64_t y = entry_y(e);
+  const int64_t wy = (int64_t)w * y;
+  const uint8_t* rowp = a.codes + (size_t)entry_row(e) * a.C;
+  const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
+  uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
+  uint32_t* hN = reinterpret_cast<uint32_t*>(area);              // [256]
+  int64_t* hS = reinterpret_cast<int64_t*>(area + 1024);          // [256]
+  uint32_t* mask = reinterpret_cast<uint32_t*>(area + 3072);      // [8]
+  uint32_t* dN = reinterpret_cast<uint32_t*>(area + 3104);        // [64]
+  int64_t* dS = reinterpret_cast<int64_t*>(area + 3360);          // [64]
+  uint32_t* dC = reinterpret_cast<uint32_t*>(area + 3872);        // [64]
+
+  double best = -1.0;
+  uint32_t best_cb = 0xFFFFFFFFu;
+  uint32_t c_next = rfl(cand[0]);
+  uint32_t code_next = valid ? rowp[c_next] : 0u;
+  for (int i = 0; i < mtry; ++i) {
+    const uint32_t c = c_next, code = code_next;
+    if (i + 1 < mtry) {  // fetch the next column's codes while this one is scanned
+      c_next = rfl(cand[i + 1]);
+      code_next = valid ? rowp[c_next] : 0u;
+    }
+    if (valid) {
+      hN[code] = 0;
+      hS[code] = 0;
+    }
+    if (lane < 8) mask[lane] = 0;
+    wave_lds_sync();
+    if (valid) {
+      atomicAdd(&hN[code], w);
+      atomicAdd((unsigned long long*)&hS[code], (unsigned long long)wy);
+      atomicOr(&mask[code >> 5], 1u << (code & 31));
+    }
+    wave_lds_sync();
+    uint32_t below = 0, total = 0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const uint32_t word = mask[m];
+      const uint32_t cnt = (uint32_t)__popc(word);
+      below += ((uint32_t)m < (code >> 5)) ? cnt : 0u;
+      total += cnt;
+    }
+    below += (uint32_t)__popc(mask[code >> 5] & ((1u << (code & 31)) - 1u));
+    if (valid) {
+      dN[below] = hN[code];
+      dS[below] = hS[code];
+      dC[below] = code;
+    }
+    wave_lds_sync();
+    const bool have = (uint32_t)lane < total;
+    const uint32_t n_i = have ? dN[lane] : 0u;
+    const int64_t s_i = have ? dS[lane] : 0;
+    const uint32_t bin = have ? dC[lane] : 0xFFFFu;
+    const uint32_t NL = wave_incl_scan_u32(n_i);
+    const int64_t SL = wave_incl_scan<int64_t>(s_i);
+    double sc = -1.0;
+    if ((uint32_t)lane + 1 < total) sc = split_score(SL, NL, S - SL, N - NL);
+    const ArgMax am = wave_argmax(sc, (int32_t)bin);
+    if (am.score > best) {
+      best = am.score;
+      best_cb = (c << 8) | (uint32_t)am.key;
+    }
+    wave_lds_sync();
+  }
+  const bool split = best >= 0.0 && best - parent_score(S, N) > 0.0;
+  const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+  const bool left = split && valid && rowp[col] <= bin;
+  const uint32_t NL = wave_sum(left ? w : 0u);
+  const int64_t SL = wave_sum(left ? wy : (int64_t)0);
+  const uint64_t QL = wave_sum(left ? (uint64_t)(wy * y) : 0ull);
+  if (lane == 0) {
+    if (split) {
+      x.sc.dcol[k] = (uint8_t)col;
+      x.sc.dbin[k] = (uint8_t)bin;
+      x.sc.dNL[k] = NL;
+      x.sc.dSL[k] = SL;
+      x.sc.dQL[k] = QL;
+      x.sc.status[k] = kSplit;
+    } else {
+      x.sc.status[k] = kLeaf;
+    }
+  }
+  wave_lds_sync();
+}
+
 // Scan one column's histogram (B bins) with a wave: lane l owns bins
 // [l R, (l+1) R); prefix sums give the left side of every split b <= B-2.
 // Returns the wave's best (max score, lowest bin) in every lane; the left
@@ -390,11 +503,12 @@ __device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
   const GrowArgs& a = *x.a;
   const int lane = (int)lane_id();
   const int mtry = x.T->mtry;
-  const uint32_t k = rfl(x.sc.big[j]);
-  const uint32_t start = rfl(x.mstart[k]);
-  const uint32_t end = rfl(x.mend[k]);
-  const uint32_t N = rfl(x.mN[k]);
-  const int64_t S = x.mS[k];
+  const NodeDesc d = x.sc.big[j];
+  const uint32_t k = rfl(d.k);
+  const uint32_t start = rfl(d.start);
+  const uint32_t end = start + rfl(d.len);
+  const uint32_t N = rfl(d.N);
+  const int64_t S = d.S;
   const int c = (int)rfl(x.sc.cand[(size_t)k * mtry + ci]);
   const int B = a.n_bins[c];
   for (int b = lane; b < B; b += kWave) {
@@ -622,7 +736,8 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         const uint32_t N = x.mN[k];
         const int64_t S = x.mS[k];
         const uint64_t Q = x.mQ[k];
-        const uint32_t len = x.mend[k] - x.mstart[k];
+        const uint32_t st = x.mstart[k];
+        const uint32_t len = x.mend[k] - st;
         if ((int64_t)N <= T.min_node || node_is_pure(N, S, Q)) {
           sc.status[k] = kLeaf;
           continue;
@@ -632,13 +747,17 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         work_rows += len;
         ++work_nodes;
         if (len <= kSegMax) {
-          const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : 3;
+          const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
           sc.status[k] = kSmall;
-          uint32_t* list = cls == 0 ? sc.seg[0] : cls == 1 ? sc.seg[1] : cls == 2 ? sc.seg[2] : sc.seg[3];
-          list[atomicAdd(&sh.cnt[3 + cls], 1u)] = k;
+          NodeDesc* list = cls == 0   ? sc.seg[0]
+                           : cls == 1 ? sc.seg[1]
+                           : cls == 2 ? sc.seg[2]
+                           : cls == 3 ? sc.seg[3]
+                                      : sc.seg[4];
+          list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
         } else if ((int32_t)len <= a.huge_min) {
           sc.status[k] = kBig;
-          sc.big[atomicAdd(&sh.cnt[1], 1u)] = k;
+          sc.big[atomicAdd(&sh.cnt[1], 1u)] = NodeDesc{k, st, len, N, S};
         } else {
           sc.status[k] = kHuge;
           sc.huge[atomicAdd(&sh.cnt[2], 1u)] = k;
@@ -668,13 +787,15 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           small_task<8>(x, sc.seg[1], t - first[1], sh.cnt[4], wl);
         else if (t < first[3])
           small_task<16>(x, sc.seg[2], t - first[2], sh.cnt[5], wl);
-        else
+        else if (t < first[4])
           small_task<32>(x, sc.seg[3], t - first[3], sh.cnt[6], wl);
+        else
+          rank_task(x, sc.seg[4], t - first[4], sh.cnt[7], wl);
       }
     }
     __syncthreads();
     // (d) decisions of the large nodes
-    for (uint32_t j = tid; j < n_big; j += BLOCK) decide_from_recs(x, sc.big[j], sc.recs + (size_t)j * mtry, mtry);
+    for (uint32_t j = tid; j < n_big; j += BLOCK) decide_from_recs(x, sc.big[j].k, sc.recs + (size_t)j * mtry, mtry);
     __syncthreads();
     // (e) breadth-first child ids, node words, children's sums and cursors
     uint32_t n_split = 0;
