@@ -121,7 +121,7 @@ def bench_forest(args, wl_name):
 
     def step():
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
-        forest = rf.aiwc_rf_fit(codes, binner, y, prm)
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=rf.FIT_TUNE)
         rf.aiwc_rf_predict(forest, codes, out=out)
         return forest, binner
 
@@ -139,7 +139,7 @@ def bench_forest(args, wl_name):
         ev[0].record()
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
         ev[1].record()
-        forest = rf.aiwc_rf_fit(codes, binner, y, prm)
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=rf.FIT_TUNE)
         ev[2].record()
         rf.aiwc_rf_predict(forest, codes, out=out)
         ev[3].record()
@@ -218,16 +218,16 @@ def bench_grid(args):
 
     for i in range(args.warmup):
         log(f"grid warmup {i}")
-        g, _ = run(rf.FIT_FUSED)
+        g, _ = run(rf.FIT_FUSED | rf.FIT_TUNE)
         del g
     fused_ms, plain_ms, grow_ms = [], [], []
     for i in range(args.steps):
-        g, ms = run(rf.FIT_FUSED)
+        g, ms = run(rf.FIT_FUSED | rf.FIT_TUNE)
         fused_ms.append(ms)
         grow_ms.append(g.stats(0)[1])
         log(f"grid fused step {i}: {ms:.1f} ms (grow {grow_ms[-1]:.1f} ms)")
         del g
-        g, ms = run(rf.FIT_PLAIN)
+        g, ms = run(rf.FIT_PLAIN | rf.FIT_TUNE)
         plain_ms.append(ms)
         log(f"grid plain step {i}: {ms:.1f} ms")
         del g

@@ -115,6 +115,57 @@ int32_t resolve_status(const aiwc_rf_forest* fc, std::string& msg) {
   return f->fit_status;
 }
 
+int ilog2_ceil(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+// The autotuner: time every candidate launch shape on the call's first trees
+// (they are grown again by the real launch, with identical results) and keep
+// the fastest for this problem shape.
+GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, aiwc_rf_forest* F,
+                     const uint8_t* codes, int64_t n, const aiwc_rf_binner* binner, const double* y, int64_t* y_fp,
+                     const int32_t* d_train, uint32_t* queue, hipStream_t s) {
+  const int64_t n_tasks = (int64_t)F->tasks.size();
+  TuneKey key{device_info().cus, ilog2_ceil(base.n_cap), n_cols, base.bins_max, mtry_max, ilog2_ceil(n_tasks)};
+  GrowConfig best = base;
+  if (tune_lookup(key, &best)) return best;
+  const int64_t trial = std::min<int64_t>(n_tasks, 16LL * device_info().cus);
+  launch_init(F->status.p, nullptr, s);
+  launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, F->status.p, s);
+  const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max);
+  hipEvent_t e0, e1;
+  AIWC_HIP(hipEventCreate(&e0));
+  AIWC_HIP(hipEventCreate(&e1));
+  float best_ms = -1.0f;
+  for (const GrowConfig& c : tune_candidates(base)) {
+    int grid = 0;
+    try {
+      grid = grow_grid_size(c, trial, mtry_max, n_cols);
+    } catch (const Error&) {
+      continue;  // the shape does not fit this device
+    }
+    DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
+    launch_init(nullptr, queue, s);
+    AIWC_HIP(hipEventRecord(e0, s));
+    launch_grow(c, codes, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial, F->nodes.p,
+                F->node_N.p, F->n_nodes.p, F->work.p, queue, F->status.p, scratch.p, base.n_cap, mtry_max, grid, s);
+    AIWC_HIP(hipEventRecord(e1, s));
+    AIWC_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    AIWC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_store(key, best);
+  return best;
+}
+
 // Traversal trusts the node words, so it only runs on a forest whose fit
 // finished without error (waits for an asynchronous fit).
 void require_fitted(const aiwc_rf_forest* f) {
@@ -225,7 +276,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
             "n_cols must equal the binner's column count");
     require(n_forests >= 1, "n_forests must be >= 1");
-    require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC)) == 0, "unknown flag");
+    require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC | AIWC_RF_FIT_TUNE)) == 0, "unknown flag");
     hipStream_t s = as_stream(stream);
     bool need_folds = false;
     int64_t total_trees = 0;
@@ -323,9 +374,11 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     DevBuf<int64_t> y_fp((size_t)n, s);
     DevBuf<uint32_t> queue(1, s);
 
-    const GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
+    GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
     const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
     const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
+    if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p,
+                                                  d_train.p, queue.p, s);
 
     if (plain) {
       // one launch sequence per forest, as separate fits would issue them

@@ -150,6 +150,22 @@ struct GrowConfig {
   int bins_max = 256;    // largest bin count of any column
   int64_t n_cap = 0;     // largest training set of any tree
 };
+// Autotuning of the grow kernel's launch shape.  A shape is keyed by the
+// device, the training-set size class, the columns, the largest bin count,
+// the largest mtry and the task-count class; the tuned config is cached in
+// memory and, when AIWC_RF_TUNE_CACHE names a file, on disk.
+struct TuneKey {
+  int cus;
+  int n_cap_log2;
+  int cols;
+  int bins_max;
+  int mtry_max;
+  int tasks_log2;
+};
+bool tune_lookup(const TuneKey& key, GrowConfig* cfg);
+void tune_store(const TuneKey& key, const GrowConfig& cfg);
+std::vector<GrowConfig> tune_candidates(const GrowConfig& base);
+
 void launch_init(uint32_t* d_status, uint32_t* d_queue, hipStream_t s);  // either may be null
 void launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,

@@ -1,5 +1,8 @@
 // Host runtime of libaiwc_rf: errors, device properties and the device memory
 // cache that every allocation of the library goes through.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -135,6 +138,98 @@ void dev_cache_trim() {
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
   free_all_cached_locked(c);
+}
+
+}  // namespace aiwc
+
+// ---------------------------------------------------------------------------
+// Launch-shape cache of the autotuner.
+// ---------------------------------------------------------------------------
+namespace aiwc {
+namespace {
+
+std::string key_text(const TuneKey& k) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "cus=%d n=2^%d cols=%d bins=%d mtry=%d tasks=2^%d", k.cus, k.n_cap_log2, k.cols,
+                k.bins_max, k.mtry_max, k.tasks_log2);
+  return buf;
+}
+
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, std::pair<int, int>> entries;  // key -> (block, huge_min)
+};
+
+TuneCache& tune_cache() {
+  static TuneCache* c = new TuneCache();
+  return *c;
+}
+
+void load_file_locked(TuneCache& c) {
+  if (c.loaded) return;
+  c.loaded = true;
+  const char* path = std::getenv("AIWC_RF_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    // "<key> | block=<b> huge_min=<h>"
+    char* bar = std::strchr(line, '|');
+    if (!bar) continue;
+    std::string key(line, bar - line);
+    while (!key.empty() && key.back() == ' ') key.pop_back();
+    int b = 0, h = 0;
+    if (std::sscanf(bar + 1, " block=%d huge_min=%d", &b, &h) == 2) c.entries[key] = {b, h};
+  }
+  std::fclose(f);
+}
+
+}  // namespace
+
+bool tune_lookup(const TuneKey& key, GrowConfig* cfg) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  load_file_locked(c);
+  auto it = c.entries.find(key_text(key));
+  if (it == c.entries.end()) return false;
+  cfg->block = it->second.first;
+  cfg->huge_min = it->second.second;
+  return true;
+}
+
+void tune_store(const TuneKey& key, const GrowConfig& cfg) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  load_file_locked(c);
+  const std::string k = key_text(key);
+  c.entries[k] = {cfg.block, cfg.huge_min};
+  if (const char* path = std::getenv("AIWC_RF_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s | block=%d huge_min=%d\n", k.c_str(), cfg.block, cfg.huge_min);
+      std::fclose(f);
+    }
+  }
+}
+
+std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
+  std::vector<GrowConfig> out;
+  for (int block : {256, 512, 1024}) {
+    if (base.n_cap > 2048) {
+      for (int h : {2048, 4096, 8192}) {
+        GrowConfig c = base;
+        c.block = block;
+        c.huge_min = h;
+        out.push_back(c);
+      }
+    } else {
+      GrowConfig c = base;
+      c.block = block;
+      out.push_back(c);
+    }
+  }
+  return out;
 }
 
 }  // namespace aiwc

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaiwc_rf.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
-FIT_FUSED, FIT_PLAIN, FIT_ASYNC = 0, 1, 2
+FIT_FUSED, FIT_PLAIN, FIT_ASYNC, FIT_TUNE = 0, 1, 2, 4
 LEAF = 255
 MAX_ROWS = 1 << 18
 

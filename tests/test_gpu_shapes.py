@@ -1,0 +1,62 @@
+"""Launch shapes never change results: every workgroup size and huge-node limit,
+and the autotuned choice, grow the same forest bit for bit (and match the oracle)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1811_00156_amd import synth
+from tests._gpu import assert_tree_equal, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    ds = synth.small(n_vec=1500, n_devices=6, p_ln=6, p_u=4, seed=21)  # 9000 rows
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 256)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 6, 4, 3, seed=9)
+    return rf, ds, ob, of
+
+
+def fit_with(rf, ds, ob, env, flags=0):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+        return rf.aiwc_rf_fit(to_dev(ob.codes), binner, to_dev(ds.y), rf.make_params(6, 4, 3, True, 9), flags=flags)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("block", ["256", "512", "1024"])
+@pytest.mark.parametrize("huge_min", ["2048", "4096", "100000"])
+def test_shape_invariance(setup, block, huge_min):
+    rf, ds, ob, of = setup
+    log(f"shape block={block} huge_min={huge_min}")
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": huge_min})
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"block {block} huge_min {huge_min} tree {t}")
+
+
+def test_autotuned_fit_matches(setup):
+    rf, ds, ob, of = setup
+    f = fit_with(rf, ds, ob, {}, flags=rf.FIT_TUNE)
+    g = fit_with(rf, ds, ob, {}, flags=rf.FIT_TUNE)  # second call: cached shape
+    for t in range(6):
+        assert_tree_equal(f.export(0, t, t + 1)[0], of.tree(t), f"tuned tree {t}")
+        assert_tree_equal(g.export(0, t, t + 1)[0], of.tree(t), f"cached tuned tree {t}")
+    codes = to_dev(ob.codes)
+    _, yhat = __import__("oracle.oracle", fromlist=["predict"]).predict(of, ob.codes)
+    assert np.array_equal(rf.aiwc_rf_predict(f, codes).cpu().numpy().view(np.uint64), yhat.view(np.uint64))
