@@ -232,6 +232,18 @@ def bench_grid(args):
         log(f"grid plain step {i}: {ms:.1f} ms")
         del g
     f_ms, p_ms = float(np.median(fused_ms)), float(np.median(plain_ms))
+    # out-of-bag scoring of every forest of the grid (the tuning objective), after the fit
+    g, _ = run(rf.FIT_FUSED | rf.FIT_TUNE)
+    oob_ms = []
+    for i in range(max(args.steps, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = rf.aiwc_rf_oob_error(g, codes, y)
+        oob_ms.append((time.perf_counter() - t0) * 1000.0)
+    best = int(np.argmin(o.mse))
+    log(f"grid oob: {float(np.median(oob_ms)):.1f} ms; lowest OOB MSE {o.mse[best]:.4f} at forest {best} "
+        f"(fold {combos[best][0]}, mtry {combos[best][1]}, min.node.size {combos[best][2]})")
+    del g
     res = {
         "metric": METRIC, "value": rows_trees / (f_ms / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f_ms, "higher_is_better": True, "scaling": "weak",
@@ -240,6 +252,7 @@ def bench_grid(args):
                                "= 1700 forests x 256 trees, one fused launch", "forests": len(params)},
         "plain_ms": p_ms, "plain_rows_trees_per_s": rows_trees / (p_ms / 1000.0), "fused_speedup": p_ms / f_ms,
         "grow_kernel_ms": float(np.median(grow_ms)),
+        "oob_ms": float(np.median(oob_ms)), "oob_rows_trees_per_s": rows_trees / (float(np.median(oob_ms)) / 1000.0),
     }
     if not args.no_cpu_baseline:
         from oracle import oracle as O

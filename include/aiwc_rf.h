@@ -181,6 +181,31 @@ int aiwc_rf_predict(const aiwc_rf_forest* forest, int32_t forest_index, const ui
 int aiwc_rf_predict_sum(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
                         int32_t tree_end, const uint8_t* codes, int64_t n, int64_t* sum_out, void* stream);
 
+/* Out-of-bag error (Sec. III-B: the objective the parameter search minimises;
+ * Sec. III-C).  For forests [forest_begin, forest_end) of a fit, every training
+ * row is predicted by the trees whose bootstrap sample left it out.  Outputs, any
+ * of which may be NULL: oob_sum_out / oob_count_out (device; one entry per
+ * training row of each forest in turn, rows in the order of the forest's training
+ * list) get the exact int64 sum of those trees' leaf values (units 2^-32) and
+ * their number; mse_host / mae_host / rows_host (forest_end - forest_begin
+ * entries) get the mean squared and mean absolute difference between
+ * (sum * 2^-32) / count and y over the rows with count > 0, and that number of
+ * rows (0 when no tree left a row out, e.g. without bootstrap).  codes and
+ * y_log10 must be the arrays the forest was fitted on.  Synchronous. */
+int aiwc_rf_oob_error(const aiwc_rf_forest* forest, int32_t forest_begin, int32_t forest_end, const uint8_t* codes,
+                      const double* y_log10, int64_t* oob_sum_out, int32_t* oob_count_out, double* mse_host,
+                      double* mae_host, int64_t* rows_host, void* stream);
+
+/* Device selection (Sec. VI: the model is to tell a scheduler on which device a
+ * kernel runs fastest).  feature_codes holds m kernels' AIWC feature codes only,
+ * m x (n_cols - 1) uint8 row-major (device); every device id 0 .. D-1 (D = the
+ * bin count of the device column, the last code column) is appended to each of
+ * them and predicted.  times_out (m x D float64, device, or NULL) receives the
+ * predicted log10 times, best_out (m int32, device) the device with the smallest
+ * prediction, the lowest id on ties.  Asynchronous on `stream`. */
+int aiwc_rf_select_device(const aiwc_rf_forest* forest, int32_t forest_index, const uint8_t* feature_codes,
+                          int64_t m, double* times_out, int32_t* best_out, void* stream);
+
 /* ------------------------------------------------------------------------------
  * Serving (the scheduler-facing use of Sec. VI): a resident forest answers a
  * stream of prediction requests of different sizes.  Requests are admitted while

@@ -55,8 +55,9 @@ def configure(L):
     L.oracle_rf_y_fixed.argtypes = [P, i64, P]
     L.oracle_rf_fit.argtypes = [P, i64, i32, P, P, P, i64, P, i32, i32, i64, P, P, P, P, P, P, i32]
     L.oracle_rf_predict.argtypes = [P, i64, i32, i32, i64, P, P, P, P, P, P]
+    L.oracle_rf_oob.argtypes = [P, i32, P, P, i64, P, i32, i64, P, P, P, P, P, P, P, P, P]
     for f in ("oracle_rf_bin", "oracle_rf_bin_apply", "oracle_rf_y_fixed", "oracle_rf_fit",
-              "oracle_rf_predict"):
+              "oracle_rf_predict", "oracle_rf_oob"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -194,3 +195,35 @@ def predict(forest: Forest, codes: np.ndarray):
     _check(lib().oracle_rf_predict(_p(codes), m, C, k, forest.capacity, _p(forest.col), _p(forest.bin),
                                    _p(forest.left), _p(forest.q), _p(P), _p(yhat)), "oracle_rf_predict")
     return P, yhat
+
+
+def oob(forest: Forest, codes: np.ndarray, y: np.ndarray, mtry: int, min_node_size: int, seed: int = 1,
+        bootstrap: bool = True, train_rows: np.ndarray | None = None):
+    """Out-of-bag sums, counts and (mse, mae, rows) of a forest grown by fit() over all its trees."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    n, C = codes.shape
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
+    n_train = n if tr is None else tr.shape[0]
+    assert forest.tree_begin == 0
+    k = forest.n_nodes.shape[0]
+    P = np.zeros(n_train, np.int64)
+    cnt = np.zeros(n_train, np.int32)
+    mse, mae, m = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    prm = Params(forest.num_trees, mtry, min_node_size, 1 if bootstrap else 0, seed)
+    _check(lib().oracle_rf_oob(_p(codes), C, _p(y), _p(tr), n_train, ctypes.byref(prm), k, forest.capacity,
+                               _p(forest.col), _p(forest.bin), _p(forest.left), _p(forest.q), _p(P), _p(cnt),
+                               ctypes.byref(mse), ctypes.byref(mae), ctypes.byref(m)), "oracle_rf_oob")
+    return P, cnt, (mse.value, mae.value, m.value)
+
+
+def select_device(forest: Forest, feature_codes: np.ndarray, n_devices: int):
+    """Predicted log10 time of every kernel on every device, and the fastest device
+    (lowest id on ties): each kernel's feature codes with device code d appended."""
+    fc = np.ascontiguousarray(feature_codes, dtype=np.uint8)
+    m = fc.shape[0]
+    expanded = np.concatenate([np.repeat(fc, n_devices, axis=0),
+                               np.tile(np.arange(n_devices, dtype=np.uint8), m)[:, None]], axis=1)
+    _, yhat = predict(forest, expanded)
+    times = yhat.reshape(m, n_devices)
+    return np.argmin(times, axis=1).astype(np.int32), times

@@ -427,3 +427,53 @@ int oracle_rf_predict(const uint8_t* codes, int64_t m, int32_t n_cols, int32_t n
   }
   return ORACLE_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Out-of-bag error (the tuning objective of Sec. III-B): each training row is
+ * predicted only by the trees whose bootstrap sample (reading R4) left it out.
+ * ------------------------------------------------------------------------- */
+int oracle_rf_oob(const uint8_t* codes, int32_t n_cols, const double* y, const int64_t* train_rows, int64_t n_train,
+                  const oracle_rf_params* prm, int32_t n_trees, int64_t capacity, const uint8_t* col,
+                  const uint8_t* bin, const int32_t* left, const int64_t* q, int64_t* P, int32_t* cnt, double* mse,
+                  double* mae, int64_t* m) {
+  if (!codes || !y || !prm || !col || !bin || !left || !q || !P || !cnt || n_train < 1 || n_trees < 1)
+    return ORACLE_EINVAL;
+  int64_t* w = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_train);
+  if (!w) return ORACLE_ENOMEM;
+  for (int64_t i = 0; i < n_train; i++) {
+    P[i] = 0;
+    cnt[i] = 0;
+  }
+  for (int32_t t = 0; t < n_trees; t++) {
+    for (int64_t i = 0; i < n_train; i++) w[i] = prm->bootstrap ? 0 : 1;
+    if (prm->bootstrap)
+      for (int64_t j = 0; j < n_train; j++)
+        w[scale_draw(philox_draw(prm->seed, TAG_BOOTSTRAP, 0, (uint64_t)t, (uint64_t)j), (uint64_t)n_train)] += 1;
+    const int64_t base = (int64_t)t * capacity;
+    for (int64_t i = 0; i < n_train; i++) {
+      if (w[i] != 0) continue;
+      const int64_t row = train_rows ? train_rows[i] : i;
+      int64_t node = 0;
+      while (col[base + node] != LEAF_COL)
+        node = codes[row * n_cols + col[base + node]] <= bin[base + node] ? left[base + node]
+                                                                          : left[base + node] + 1;
+      P[i] += q[base + node];
+      cnt[i] += 1;
+    }
+  }
+  double sq = 0.0, ab = 0.0;
+  int64_t rows = 0;
+  for (int64_t i = 0; i < n_train; i++) {
+    if (cnt[i] == 0) continue;
+    const int64_t row = train_rows ? train_rows[i] : i;
+    double e = ((double)P[i] * 0x1p-32) / (double)cnt[i] - y[row];
+    sq += e * e;
+    ab += fabs(e);
+    rows++;
+  }
+  *mse = rows ? sq / (double)rows : 0.0;
+  *mae = rows ? ab / (double)rows : 0.0;
+  *m = rows;
+  free(w);
+  return ORACLE_OK;
+}

@@ -77,6 +77,16 @@ int oracle_rf_predict(const uint8_t* codes, int64_t m, int32_t n_cols, int32_t n
                       int64_t capacity, const uint8_t* col, const uint8_t* bin, const int32_t* left,
                       const int64_t* q, int64_t* P, double* yhat);
 
+/* Out-of-bag error of trees 0 .. n_trees-1 of a forest (slots as oracle_rf_fit
+ * writes them, grown with the same training rows and parameters).  For training
+ * row i: P[i] = sum of q over the trees whose bootstrap sample did not draw it,
+ * cnt[i] = their number.  Over the rows with cnt > 0, in row order: mse = mean of
+ * ((P * 2^-32) / cnt - y)^2, mae = mean of the absolute difference, m = rows. */
+int oracle_rf_oob(const uint8_t* codes, int32_t n_cols, const double* y, const int64_t* train_rows, int64_t n_train,
+                  const oracle_rf_params* prm, int32_t n_trees, int64_t capacity, const uint8_t* col,
+                  const uint8_t* bin, const int32_t* left, const int64_t* q, int64_t* P, int32_t* cnt, double* mse,
+                  double* mae, int64_t* m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -150,7 +150,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
     launch_init(nullptr, queue, s);
     AIWC_HIP(hipEventRecord(e0, s));
     launch_grow(c, codes, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial, F->nodes.p,
-                F->node_N.p, F->n_nodes.p, F->work.p, queue, F->status.p, scratch.p, base.n_cap, mtry_max, grid, s);
+                F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p, base.n_cap, mtry_max, grid, s);
     AIWC_HIP(hipEventRecord(e1, s));
     AIWC_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -320,13 +320,16 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     std::unique_ptr<aiwc_rf_forest> F(new aiwc_rf_forest());
     AIWC_HIP(hipGetDevice(&F->device));
     F->n_cols = n_cols;
+    F->n_bins = binner->n_bins;
     F->params.assign(params_host, params_host + n_forests);
     F->tasks.reserve((size_t)total_trees);
-    int64_t pool = 0, n_cap = 1;
+    int64_t pool = 0, n_cap = 1, inbag_words = 0;
     for (int32_t f = 0; f < n_forests; ++f) {
       const aiwc_rf_params& P = params_host[f];
       const auto& L = lists[heldout_fold_host ? heldout_fold_host[f] : -1];
       F->first_task.push_back((int64_t)F->tasks.size());
+      F->n_train.push_back(L.second);
+      F->train_off.push_back(L.first);
       const int64_t cap = 2 * (int64_t)L.second - 1;
       n_cap = std::max<int64_t>(n_cap, L.second);
       for (int32_t t = 0; t < P.num_trees; ++t) {
@@ -341,6 +344,8 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         T.train_off = L.first;
         T.node_base = pool;
         T.capacity = cap;
+        T.inbag_off = P.bootstrap ? inbag_words : -1;
+        if (P.bootstrap) inbag_words += (L.second + 63) / 64;
         pool += cap;
         F->tasks.push_back(T);
       }
@@ -368,9 +373,11 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
       // the staging copies above read pageable host memory; wait before it goes out of scope
       AIWC_HIP(hipStreamSynchronize(s));
     }
-    DevBuf<int32_t> d_train(train_rows.size(), s);
+    F->train_rows.reset(train_rows.size(), s);
+    DevBuf<int32_t>& d_train = F->train_rows;
     if (!train_rows.empty())
       AIWC_HIP(hipMemcpyAsync(d_train.p, train_rows.data(), sizeof(int32_t) * train_rows.size(), hipMemcpyHostToDevice, s));
+    F->inbag.reset((size_t)inbag_words, s);
     DevBuf<int64_t> y_fp((size_t)n, s);
     DevBuf<uint32_t> queue(1, s);
 
@@ -393,7 +400,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         launch_init(nullptr, queue.p, s);
         launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
         launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, queue.p, F->status.p, scratch.p,
+                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, F->inbag.p, queue.p, F->status.p, scratch.p,
                     n_cap, mtry_max, grid, s);
       }
       AIWC_HIP(hipEventRecord(F->grow_end, s));
@@ -415,7 +422,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
           launch_init(F->status.p, queue.p, cs);
           launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, cs);
           launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                      F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, queue.p, F->status.p, scratch.p, n_cap,
+                      F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap,
                       mtry_max, grid, cs);
         } catch (...) {
           (void)hipStreamEndCapture(cs, &graph);
@@ -440,7 +447,7 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
         AIWC_HIP(hipEventRecord(F->grow_begin, s));
         launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
+                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
                     grid, s);
         AIWC_HIP(hipEventRecord(F->grow_end, s));
       }
@@ -600,6 +607,73 @@ int aiwc_rf_predict_sum(const aiwc_rf_forest* f, int32_t forest_index, int32_t t
     require_fitted(f);
     launch_predict(f->nodes.p, f->node_base.p, (int32_t)(t0 + tree_begin), (int32_t)(t0 + tree_end), codes, n,
                    f->n_cols, sum_out, nullptr, nt, s);
+  });
+}
+
+int aiwc_rf_oob_error(const aiwc_rf_forest* f, int32_t forest_begin, int32_t forest_end, const uint8_t* codes,
+                      const double* y_log10, int64_t* oob_sum_out, int32_t* oob_count_out, double* mse_host,
+                      double* mae_host, int64_t* rows_host, void* stream) {
+  return guard([&] {
+    require(f != nullptr, "forest is NULL");
+    require(forest_begin >= 0 && forest_begin < forest_end && forest_end <= (int32_t)f->params.size(),
+            "forest range out of bounds");
+    require(codes && y_log10, "null pointer argument");
+    hipStream_t s = as_stream(stream);
+    require_fitted(f);
+    const int32_t nf = forest_end - forest_begin;
+    std::vector<OobForest> fr((size_t)nf);
+    int64_t rows = 0;
+    int32_t max_n = 1;
+    for (int32_t k = 0; k < nf; ++k) {
+      const int32_t fi = forest_begin + k;
+      fr[k].first_task = f->first_task[fi];
+      fr[k].num_trees = f->params[fi].num_trees;
+      fr[k].n_train = f->n_train[fi];
+      fr[k].train_off = f->train_off[fi];
+      fr[k].row_off = rows;
+      rows += f->n_train[fi];
+      max_n = std::max(max_n, f->n_train[fi]);
+    }
+    DevBuf<OobForest> d_fr((size_t)nf, s);
+    AIWC_HIP(hipMemcpyAsync(d_fr.p, fr.data(), sizeof(OobForest) * nf, hipMemcpyHostToDevice, s));
+    DevBuf<int64_t> sum_tmp(oob_sum_out ? 0 : (size_t)rows, s);
+    DevBuf<int32_t> cnt_tmp(oob_count_out ? 0 : (size_t)rows, s);
+    const int32_t blocks = (max_n + 255) / 256;
+    DevBuf<double> partial((size_t)3 * nf * blocks, s);
+    DevBuf<double> result((size_t)3 * nf, s);
+    launch_oob(f->nodes.p, f->d_tasks.p, f->node_base.p, f->inbag.p, f->train_rows.p, d_fr.p, nf, max_n, codes,
+               f->n_cols, y_log10, oob_sum_out ? oob_sum_out : sum_tmp.p, oob_count_out ? oob_count_out : cnt_tmp.p,
+               partial.p, result.p, s);
+    std::vector<double> res((size_t)3 * nf);
+    AIWC_HIP(hipMemcpyAsync(res.data(), result.p, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+    AIWC_HIP(hipStreamSynchronize(s));
+    for (int32_t k = 0; k < nf; ++k) {
+      if (mse_host) mse_host[k] = res[3 * k];
+      if (mae_host) mae_host[k] = res[3 * k + 1];
+      if (rows_host) rows_host[k] = (int64_t)res[3 * k + 2];
+    }
+  });
+}
+
+int aiwc_rf_select_device(const aiwc_rf_forest* f, int32_t forest_index, const uint8_t* feature_codes, int64_t m,
+                          double* times_out, int32_t* best_out, void* stream) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    require(m >= 0, "m must be >= 0");
+    if (m == 0) return;
+    require(feature_codes && best_out, "null pointer argument");
+    require(f->n_cols >= 2, "the forest has no feature column besides the device");
+    hipStream_t s = as_stream(stream);
+    const int32_t D = f->n_bins.back();
+    const int32_t nt = f->params[forest_index].num_trees;
+    const int64_t t0 = f->first_task[forest_index];
+    require_fitted(f);
+    const int64_t rows = m * D;
+    DevBuf<uint8_t> expanded((size_t)(rows * f->n_cols), s);
+    DevBuf<int64_t> sum((size_t)rows, s);
+    DevBuf<double> times_tmp(times_out ? 0 : (size_t)rows, s);
+    launch_select_device(f->nodes.p, f->node_base.p, (int32_t)t0, (int32_t)(t0 + nt), feature_codes, m, f->n_cols, D,
+                         nt, expanded.p, sum.p, times_out ? times_out : times_tmp.p, best_out, s);
   });
 }
 

@@ -151,6 +151,7 @@ struct GrowArgs {
   uint32_t* node_N;
   int32_t* n_nodes;
   int64_t* work;  // per task: searched rows, searched nodes, partitioned rows, levels
+  uint64_t* inbag;
   uint32_t* queue;
   uint32_t* status;
   uint8_t* scratch;
@@ -692,6 +693,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
   for (int64_t base = 0; base < n; base += BLOCK) {
     const int64_t i = base + tid;
     const uint32_t c = i < n ? sc.cnt[i] : 0u;
+    // in-bag bitmap: this wave's 64 consecutive rows form one word
+    const uint64_t bits = __ballot(c > 0);
+    const int64_t wbase = base + (int64_t)(tid / kWave) * kWave;
+    if (lane_id() == 0 && T.inbag_off >= 0 && wbase < n) a.inbag[T.inbag_off + wbase / kWave] = bits;
     uint32_t total;
     const uint32_t pos = block_exscan<BLOCK>(c > 0 ? 1u : 0u, sh.tmp, total) + n_inbag;
     if (c > 0) {
@@ -1046,8 +1051,9 @@ int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int
 
 void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint32_t* d_queue,
-                 uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s) {
+                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
+                 uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,
+                 hipStream_t s) {
   GrowArgs a;
   a.codes = codes;
   a.C = C;
@@ -1060,6 +1066,7 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const i
   a.node_N = node_N;
   a.n_nodes = n_nodes;
   a.work = work;
+  a.inbag = inbag;
   a.queue = d_queue;
   a.status = d_status;
   a.scratch = scratch;

@@ -97,6 +97,7 @@ struct TreeTask {
   int64_t train_off;  // offset into the training-row lists, -1 = rows 0..n_train-1
   int64_t node_base;  // first node of the tree's slot in the node pool
   int64_t capacity;   // node slots reserved for the tree (2 n_train - 1)
+  int64_t inbag_off;  // first 64-bit word of the tree's in-bag bitmap over its training rows, -1 = none
 };
 
 // Status bits a fit raises on the device.
@@ -128,6 +129,11 @@ struct aiwc_rf_forest {
   int32_t fit_status = 0;                  // resolved status after wait
   bool waited = false;
   int64_t pool_nodes = 0;
+  std::vector<int32_t> n_bins;             // bin count of every code column (device column last)
+  aiwc::DevBuf<int32_t> train_rows;        // training-row lists of the forests that hold out a fold
+  aiwc::DevBuf<uint64_t> inbag;            // per tree: bit i set if training row i is in its bootstrap sample
+  std::vector<int32_t> n_train;            // per forest
+  std::vector<int64_t> train_off;          // per forest, -1 = rows 0 .. n_train-1
 };
 
 namespace aiwc {
@@ -174,13 +180,32 @@ size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
 void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint32_t* d_queue,
-                 uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid, hipStream_t s);
+                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
+                 uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,
+                 hipStream_t s);
+
+// oob.hip: out-of-bag sums of every training row of forests [f0, f1), then
+// the squared and absolute errors of the out-of-bag predictions per forest.
+struct OobForest {
+  int64_t first_task;
+  int32_t num_trees;
+  int32_t n_train;
+  int64_t train_off;  // -1 = rows 0 .. n_train-1
+  int64_t row_off;    // first slot of this forest's rows in the per-row outputs
+};
+void launch_oob(const uint64_t* nodes, const TreeTask* tasks, const int64_t* node_base, const uint64_t* inbag,
+                const int32_t* train_rows, const OobForest* forests, int32_t n_forests, int32_t max_n_train,
+                const uint8_t* codes, int32_t C, const double* y, int64_t* sum, int32_t* count, double* partial,
+                double* result, hipStream_t s);
 
 // predict.hip
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                     const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,
                     hipStream_t s);
+
+void launch_select_device(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
+                          const uint8_t* feature_codes, int64_t m, int32_t C, int32_t n_devices, int32_t num_trees,
+                          uint8_t* expanded, int64_t* sum, double* times, int32_t* best, hipStream_t s);
 
 // Device properties of the current device (cached).
 struct DeviceInfo {

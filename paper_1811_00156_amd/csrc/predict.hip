@@ -78,7 +78,42 @@ __global__ void k_finalize(const int64_t* sum, int64_t n, double trees, double* 
     y[i] = ((double)sum[i] * 0x1p-32) / trees;
 }
 
+// Row i * D + d of the expanded matrix = kernel i's feature codes + device d.
+__global__ void k_expand_devices(const uint8_t* feat, int64_t m, int32_t C, int32_t D, uint8_t* out) {
+  const int64_t total = m * D * C;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = g / C;
+    const int32_t j = (int32_t)(g % C);
+    const int64_t i = row / D;
+    out[g] = j < C - 1 ? feat[i * (C - 1) + j] : (uint8_t)(row % D);
+  }
+}
+
+// Fastest device per kernel: the smallest predicted time, the lowest id on ties.
+__global__ void k_argmin_devices(const double* times, int64_t m, int32_t D, int32_t* best) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const double* t = times + i * D;
+    int32_t b = 0;
+    for (int32_t d = 1; d < D; ++d)
+      if (t[d] < t[b]) b = d;
+    best[i] = b;
+  }
+}
+
 }  // namespace
+
+void launch_select_device(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
+                          const uint8_t* feature_codes, int64_t m, int32_t C, int32_t n_devices, int32_t num_trees,
+                          uint8_t* expanded, int64_t* sum, double* times, int32_t* best, hipStream_t s) {
+  const int64_t rows = m * n_devices;
+  const int eb = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (rows * C + 255) / 256));
+  k_expand_devices<<<eb, 256, 0, s>>>(feature_codes, m, C, n_devices, expanded);
+  AIWC_HIP(hipGetLastError());
+  launch_predict(nodes, node_base, tree_begin, tree_end, expanded, rows, C, sum, times, num_trees, s);
+  const int ab = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (m + 255) / 256));
+  k_argmin_devices<<<ab, 256, 0, s>>>(times, m, n_devices, best);
+  AIWC_HIP(hipGetLastError());
+}
 
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                     const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,

@@ -61,6 +61,8 @@ _sig("aiwc_rf_forest_export_host", [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_free", [_P], None)
 _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_predict_sum", [_P, _i32, _i32, _i32, _P, _i64, _P, _P])
+_sig("aiwc_rf_select_device", [_P, _i32, _P, _i64, _P, _P, _P])
+_sig("aiwc_rf_oob_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_server_create", [_P, _i32, _i64, _i32, _i32, _P])
 _sig("aiwc_rf_server_submit", [_P, _P, _i64, _P, _P])
 _sig("aiwc_rf_server_poll", [_P, _P, _P, _i32, _P])
@@ -72,7 +74,7 @@ _sig("aiwc_rf_last_error", [], ctypes.c_char_p)
 SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
            "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
-           "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
+           "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
 
 
@@ -280,6 +282,59 @@ def aiwc_rf_predict_sum(forest: Forest, codes, tree_begin: int, tree_end: int, f
                                   _dev(codes, torch.uint8, "codes"), n, _dev(out, torch.int64, "out"),
                                   _stream(stream)), "aiwc_rf_predict_sum")
     return out
+
+
+@dataclass
+class OobResult:
+    sums: object  # int64 device tensor: out-of-bag leaf sums per training row (forests in turn)
+    counts: object  # int32 device tensor: out-of-bag trees per training row
+    mse: np.ndarray  # per forest
+    mae: np.ndarray
+    rows: np.ndarray
+
+
+def aiwc_rf_oob_error(forest: Forest, codes, y_log10, forest_begin: int = 0, forest_end: int | None = None,
+                      n_train=None, stream=None) -> OobResult:
+    """Out-of-bag predictions and errors of forests [forest_begin, forest_end).
+
+    n_train: total training rows of those forests (sizes the per-row outputs); when
+    omitted the per-row outputs are not returned."""
+    import torch
+
+    if forest_end is None:
+        forest_end = forest.n_forests
+    nf = forest_end - forest_begin
+    mse = np.zeros(nf)
+    mae = np.zeros(nf)
+    rows = np.zeros(nf, np.int64)
+    sums = counts = None
+    if n_train is not None:
+        sums = torch.empty(n_train, dtype=torch.int64, device=codes.device)
+        counts = torch.empty(n_train, dtype=torch.int32, device=codes.device)
+    _check(_L.aiwc_rf_oob_error(forest.handle, forest_begin, forest_end, _dev(codes, torch.uint8, "codes"),
+                                _dev(y_log10, torch.float64, "y"),
+                                None if sums is None else _dev(sums, torch.int64, "sums"),
+                                None if counts is None else _dev(counts, torch.int32, "counts"),
+                                _host(mse), _host(mae), _host(rows), _stream(stream)), "aiwc_rf_oob_error")
+    return OobResult(sums, counts, mse, mae, rows)
+
+
+def aiwc_rf_select_device(forest: Forest, feature_codes, forest_index: int = 0, n_devices: int | None = None,
+                          times=None, best=None, stream=None):
+    """Fastest device per kernel from its feature codes alone: (best int32[m], times float64[m, D])."""
+    import torch
+
+    m = feature_codes.shape[0]
+    if n_devices is None:
+        raise ValueError("n_devices (the device column's bin count) is required to size the outputs")
+    if times is None:
+        times = torch.empty((m, n_devices), dtype=torch.float64, device=feature_codes.device)
+    if best is None:
+        best = torch.empty(m, dtype=torch.int32, device=feature_codes.device)
+    _check(_L.aiwc_rf_select_device(forest.handle, forest_index, _dev(feature_codes, torch.uint8, "feature_codes"), m,
+                                    _dev(times, torch.float64, "times"), _dev(best, torch.int32, "best"),
+                                    _stream(stream)), "aiwc_rf_select_device")
+    return best, times
 
 
 @dataclass

@@ -1,0 +1,129 @@
+"""GPU parity of the out-of-bag error and of device selection (Sec. III-B, III-C).
+
+Per-row out-of-bag leaf sums and tree counts are integers and must match the
+oracle bit for bit; so must the device-selection times (the same correctly
+rounded operations as the forest mean) and the chosen devices.  The mean squared
+and absolute errors are sums of n non-negative binary64 terms taken in different
+orders on the two sides (row order in the oracle, wave and workgroup trees on the
+GPU); each is within n * 2^-53 of the exact mean in relative terms, so they may
+differ by at most 2 n 2^-53 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_1811_00156_amd import synth
+from tests._gpu import log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_00156_amd import rf as _rf
+
+    return _rf
+
+
+@pytest.fixture(scope="module")
+def d1b(oracle):
+    ds = synth.d1()
+    return ds, oracle.bin(ds.X, ds.device, ds.n_devices, 64)
+
+
+def _close(g, o, n):
+    tol = 2 * max(n, 1) * 2.0 ** -53
+    return abs(g - o) <= tol * abs(o)
+
+
+def test_oob_single_forest(rf, oracle, d1b):
+    log("oob single forest d1 50 trees")
+    ds, ob = d1b
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    forest = rf.aiwc_rf_fit(codes, binner, y, rf.make_params(50, 6, 5, True, 11))
+    res = rf.aiwc_rf_oob_error(forest, codes, y, n_train=ds.n)
+    of = oracle.fit(ob.codes, ob.n_bins, ds.y, 50, 6, 5, seed=11)
+    P, cnt, (mse, mae, m) = oracle.oob(of, ob.codes, ds.y, 6, 5, seed=11)
+    assert np.array_equal(res.sums.cpu().numpy(), P)
+    assert np.array_equal(res.counts.cpu().numpy(), cnt)
+    assert res.rows[0] == m
+    assert _close(res.mse[0], mse, m) and _close(res.mae[0], mae, m)
+
+
+def test_oob_grid_with_folds(rf, oracle, d1b):
+    """A cross-validation x mtry x min.node.size grid, scored on a sub-range of forests."""
+    log("oob grid d1 folds")
+    ds, ob = d1b
+    folds = synth.cv_folds()
+    combos = [(0, 3, 1, True), (5, 12, 5, True), (-1, 35, 9, True), (7, 6, 3, False), (9, 1, 1, True)]
+    params = [rf.make_params(12, m, mn, b, 3) for _, m, mn, b in combos]
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    forest = rf.aiwc_rf_fit(codes, binner, y, params, fold_id=to_dev(folds), heldout_fold=[c[0] for c in combos])
+    trains = [np.arange(ds.n) if f < 0 else np.nonzero(folds != f)[0] for f, _, _, _ in combos]
+    for begin, end in ((0, 5), (1, 4), (4, 5)):
+        total = sum(t.shape[0] for t in trains[begin:end])
+        res = rf.aiwc_rf_oob_error(forest, codes, y, begin, end, n_train=total)
+        sums, counts = res.sums.cpu().numpy(), res.counts.cpu().numpy()
+        off = 0
+        for k in range(begin, end):
+            f, m_, mn, b = combos[k]
+            of = oracle.fit(ob.codes, ob.n_bins, ds.y, 12, m_, mn, seed=3, bootstrap=b, train_rows=trains[k])
+            P, cnt, (mse, mae, m) = oracle.oob(of, ob.codes, ds.y, m_, mn, seed=3, bootstrap=b, train_rows=trains[k])
+            n = trains[k].shape[0]
+            assert np.array_equal(sums[off:off + n], P), f"forest {k}"
+            assert np.array_equal(counts[off:off + n], cnt), f"forest {k}"
+            assert res.rows[k - begin] == m
+            if m == 0:
+                assert res.mse[k - begin] == 0.0 and res.mae[k - begin] == 0.0
+            else:
+                assert _close(res.mse[k - begin], mse, m) and _close(res.mae[k - begin], mae, m)
+            off += n
+    # scores only, no per-row outputs
+    res = rf.aiwc_rf_oob_error(forest, codes, y)
+    assert res.sums is None and res.rows[3] == 0 and res.rows[0] > 0
+
+
+def test_oob_errors(rf, d1b):
+    ds, ob = d1b
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    forest = rf.aiwc_rf_fit(codes, binner, y, rf.make_params(2, 3, 5, True, 1))
+    for b, e in ((0, 2), (1, 1), (-1, 1)):
+        with pytest.raises(rf.RFError):
+            rf.aiwc_rf_oob_error(forest, codes, y, b, e)
+
+
+@pytest.mark.parametrize("m", [1, 63, 1000])
+def test_select_device(rf, oracle, d1b, m):
+    log(f"select device m={m}")
+    ds, ob = d1b
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    forest = rf.aiwc_rf_fit(codes, binner, y, rf.make_params(32, 10, 5, True, 4))
+    of = oracle.fit(ob.codes, ob.n_bins, ds.y, 32, 10, 5, seed=4)
+    rng = np.random.default_rng(m)
+    feats = np.ascontiguousarray(ob.codes[rng.integers(0, ds.n, size=m), :-1])
+    best, times = rf.aiwc_rf_select_device(forest, to_dev(feats), n_devices=ds.n_devices)
+    ob_best, ob_times = oracle.select_device(of, feats, ds.n_devices)
+    assert np.array_equal(times.cpu().numpy().view(np.uint64), ob_times.view(np.uint64))
+    assert np.array_equal(best.cpu().numpy(), ob_best)
+
+
+def test_select_device_in_grid(rf, oracle, d1b):
+    """Selection reads the trees of the requested forest of a grid."""
+    ds, ob = d1b
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    params = [rf.make_params(5, 4, 3, True, 8), rf.make_params(7, 20, 1, True, 9)]
+    forest = rf.aiwc_rf_fit(codes, binner, y, params)
+    feats = np.ascontiguousarray(ob.codes[::50, :-1])
+    of = oracle.fit(ob.codes, ob.n_bins, ds.y, 7, 20, 1, seed=9)
+    best, times = rf.aiwc_rf_select_device(forest, to_dev(feats), forest_index=1, n_devices=ds.n_devices)
+    ob_best, ob_times = oracle.select_device(of, feats, ds.n_devices)
+    assert np.array_equal(times.cpu().numpy().view(np.uint64), ob_times.view(np.uint64))
+    assert np.array_equal(best.cpu().numpy(), ob_best)

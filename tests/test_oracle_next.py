@@ -1,0 +1,129 @@
+"""Pins of the oracle's out-of-bag error and device selection (Sec. III-B, III-C).
+
+The out-of-bag sums are re-derived here from NumPy's own Philox stream and a
+Python traversal of the exported trees; the errors are re-derived in exact
+rational arithmetic.  Device selection is checked on hand-built trees whose
+answer is known, and by brute force against per-row traversal."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1811_00156_amd import synth
+from _ref import bootstrap_weights
+
+
+def _leaf_q(tree, row):
+    node = 0
+    while tree["col"][node] != 255:
+        c = tree["col"][node]
+        node = tree["left"][node] + (0 if row[c] <= tree["bin"][node] else 1)
+    return int(tree["q"][node])
+
+
+@pytest.fixture(scope="module")
+def d1_binned(oracle):
+    ds = synth.d1()
+    return ds, oracle.bin(ds.X, ds.device, ds.n_devices, 64)
+
+
+@pytest.mark.parametrize("fold", [-1, 4])
+def test_oob_matches_brute_force(oracle, d1_binned, fold):
+    ds, b = d1_binned
+    folds = synth.cv_folds()
+    train = None if fold < 0 else np.nonzero(folds != fold)[0]
+    rows = np.arange(ds.n) if train is None else train
+    T, seed = 9, 17
+    f = oracle.fit(b.codes, b.n_bins, ds.y, T, 5, 3, seed=seed, train_rows=train)
+    P, cnt, (mse, mae, m) = oracle.oob(f, b.codes, ds.y, 5, 3, seed=seed, train_rows=train)
+    n = rows.shape[0]
+    ref_P = [0] * n
+    ref_c = [0] * n
+    for t in range(T):
+        w = bootstrap_weights(seed, t, n)
+        tree = f.tree(t)
+        for i in range(n):
+            if w[i] == 0:
+                ref_P[i] += _leaf_q(tree, b.codes[rows[i]])
+                ref_c[i] += 1
+    assert P.tolist() == ref_P
+    assert cnt.tolist() == ref_c
+    used = [i for i in range(n) if ref_c[i] > 0]
+    assert m == len(used)
+    # per-row error as the method defines it (one rounding per operation), mean exactly
+    errs = [(float(ref_P[i]) * 2.0 ** -32) / float(ref_c[i]) - float(ds.y[rows[i]]) for i in used]
+    ex_mse = sum(Fraction(e) * Fraction(e) for e in errs) / len(errs)
+    ex_mae = sum(abs(Fraction(e)) for e in errs) / len(errs)
+    # row-order summation of n non-negative terms: relative error below n * 2^-53
+    tol = 2 * len(errs) * 2.0 ** -53
+    assert abs(Fraction(mse) - ex_mse) <= tol * ex_mse
+    assert abs(Fraction(mae) - ex_mae) <= tol * ex_mae
+
+
+def test_oob_fraction_near_e_inverse(oracle, d1_binned):
+    """Each row is left out of a bootstrap sample with probability (1 - 1/n)^n ~ 1/e."""
+    ds, b = d1_binned
+    T = 40
+    f = oracle.fit(b.codes, b.n_bins, ds.y, T, 8, 5, seed=5)
+    _, cnt, (_, _, m) = oracle.oob(f, b.codes, ds.y, 8, 5, seed=5)
+    p = (1 - 1 / ds.n) ** ds.n
+    frac = cnt.mean() / T
+    sd = np.sqrt(p * (1 - p) / (T * ds.n))
+    assert abs(frac - p) < 6 * sd
+    assert m == int((cnt > 0).sum())
+
+
+def test_oob_without_bootstrap_has_no_rows(oracle, d1_binned):
+    ds, b = d1_binned
+    f = oracle.fit(b.codes, b.n_bins, ds.y, 4, 8, 5, seed=5, bootstrap=False)
+    P, cnt, (mse, mae, m) = oracle.oob(f, b.codes, ds.y, 8, 5, seed=5, bootstrap=False)
+    assert m == 0 and mse == 0.0 and mae == 0.0
+    assert not cnt.any() and not P.any()
+
+
+def _hand_forest(oracle, col, bin_, left, q):
+    k = len(col)
+    return oracle.Forest(num_trees=1, tree_begin=0, capacity=k, col=np.array(col, np.uint8),
+                         bin=np.array(bin_, np.uint8), left=np.array(left, np.int32), q=np.array(q, np.int64),
+                         N=np.ones(k, np.int32), n_nodes=np.array([k], np.int64))
+
+
+def test_select_device_ties_go_to_lowest_id(oracle):
+    """A tree that never splits on the device predicts the same time everywhere."""
+    f = _hand_forest(oracle, [0, 255, 255], [3, 0, 0], [1, -1, -1], [0, 7 << 32, -(5 << 32)])
+    feats = np.array([[2, 9], [4, 1], [3, 3]], np.uint8)  # device column appended as column 2
+    best, times = oracle.select_device(f, feats, 6)
+    assert best.tolist() == [0, 0, 0]
+    assert times.tolist() == [[7.0] * 6, [-5.0] * 6, [7.0] * 6]
+
+
+def test_select_device_splits_on_device(oracle):
+    """Device ids <= 1 are slow, the rest fast except where feature 0 is large."""
+    # node 0: device <= 1 ? node 1 (leaf 3.0) : node 2; node 2: feature 0 <= 4 ? leaf -1.0 : leaf 2.5
+    f = _hand_forest(oracle, [1, 255, 0, 255, 255], [1, 0, 4, 0, 0], [1, -1, 3, -1, -1],
+                     [0, 3 << 32, 0, -(1 << 32), 5 << 31])
+    feats = np.array([[0], [4], [5], [255]], np.uint8)
+    best, times = oracle.select_device(f, feats, 4)
+    assert best.tolist() == [2, 2, 2, 2]
+    assert times[0].tolist() == [3.0, 3.0, -1.0, -1.0]
+    assert times[2].tolist() == [3.0, 3.0, 2.5, 2.5]
+    # with only devices 0 and 1 there is a tie at 3.0: the lowest id wins
+    best2, _ = oracle.select_device(f, feats, 2)
+    assert best2.tolist() == [0, 0, 0, 0]
+
+
+def test_select_device_brute_force(oracle, d1_binned):
+    ds, b = d1_binned
+    T = 6
+    f = oracle.fit(b.codes, b.n_bins, ds.y, T, 10, 5, seed=2)
+    feats = b.codes[::97, :-1]
+    best, times = oracle.select_device(f, feats, ds.n_devices)
+    trees = [f.tree(t) for t in range(T)]
+    for i in range(feats.shape[0]):
+        row_t = []
+        for d in range(ds.n_devices):
+            row = np.concatenate([feats[i], [d]]).astype(np.uint8)
+            P = sum(_leaf_q(tr, row) for tr in trees)
+            row_t.append((float(P) * 2.0 ** -32) / T)
+        assert times[i].tolist() == row_t
+        assert best[i] == min(range(ds.n_devices), key=lambda d: (row_t[d], d))
