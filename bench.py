@@ -47,6 +47,16 @@ WORKLOADS = {
 METRIC = "forest fit rows·trees/s (fused grid vs plain); predict rows/s + p99 latency"
 
 
+FIXED_SHAPE = False
+
+
+def tune_flag():
+    """FIT_TUNE unless --fixed-shape asks for the launch shape of the environment."""
+    from paper_1811_00156_amd import rf
+
+    return 0 if FIXED_SHAPE else rf.FIT_TUNE
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -121,7 +131,7 @@ def bench_forest(args, wl_name):
 
     def step():
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
-        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=rf.FIT_TUNE)
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=tune_flag())
         rf.aiwc_rf_predict(forest, codes, out=out)
         return forest, binner
 
@@ -139,7 +149,7 @@ def bench_forest(args, wl_name):
         ev[0].record()
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
         ev[1].record()
-        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=rf.FIT_TUNE)
+        forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=tune_flag())
         ev[2].record()
         rf.aiwc_rf_predict(forest, codes, out=out)
         ev[3].record()
@@ -218,22 +228,22 @@ def bench_grid(args):
 
     for i in range(args.warmup):
         log(f"grid warmup {i}")
-        g, _ = run(rf.FIT_FUSED | rf.FIT_TUNE)
+        g, _ = run(rf.FIT_FUSED | tune_flag())
         del g
     fused_ms, plain_ms, grow_ms = [], [], []
     for i in range(args.steps):
-        g, ms = run(rf.FIT_FUSED | rf.FIT_TUNE)
+        g, ms = run(rf.FIT_FUSED | tune_flag())
         fused_ms.append(ms)
         grow_ms.append(g.stats(0)[1])
         log(f"grid fused step {i}: {ms:.1f} ms (grow {grow_ms[-1]:.1f} ms)")
         del g
-        g, ms = run(rf.FIT_PLAIN | rf.FIT_TUNE)
+        g, ms = run(rf.FIT_PLAIN | tune_flag())
         plain_ms.append(ms)
         log(f"grid plain step {i}: {ms:.1f} ms")
         del g
     f_ms, p_ms = float(np.median(fused_ms)), float(np.median(plain_ms))
     # out-of-bag scoring of every forest of the grid (the tuning objective), after the fit
-    g, _ = run(rf.FIT_FUSED | rf.FIT_TUNE)
+    g, _ = run(rf.FIT_FUSED | tune_flag())
     oob_ms = []
     for i in range(max(args.steps, 1)):
         torch.cuda.synchronize()
@@ -369,10 +379,14 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy"])
     ap.add_argument("--requests", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fixed-shape", action="store_true",
+                    help="no autotuning: grow with AIWC_RF_GROW_BLOCK / AIWC_RF_HUGE_MIN or the defaults")
     args = ap.parse_args()
+    global FIXED_SHAPE
+    FIXED_SHAPE = args.fixed_shape
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(trees shard across GPUs by design, see DESIGN.md)"}))
+                                   "(the forest shards by trees across GPUs; only the one-GPU path is built here)"}))
         sys.exit(2)
     import torch
 

@@ -68,13 +68,15 @@ int32_t status_to_code(uint32_t st, std::string& msg) {
 
 GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t>& n_bins) {
   GrowConfig cfg;
-  // large training sets: the biggest workgroups (huge-node histograms span all
-  // waves); small ones: 512 threads per tree while trees are few, 256 once there
-  // are enough trees to fill four workgroups per CU
-  if (n_cap > 16384)
-    cfg.block = 1024;
-  else
+  // large training sets: 512 threads per tree, every node above 64 rows in
+  // workgroup-wide batches; small ones: 512 threads per tree while trees are
+  // few, 256 once there are enough trees to fill four workgroups per CU
+  if (n_cap > 16384) {
+    cfg.block = 512;
+    cfg.huge_min = 64;
+  } else {
     cfg.block = n_tasks >= 4LL * device_info().cus ? 256 : 512;
+  }
   cfg.n_cap = n_cap;
   cfg.bins_max = 1;
   for (int32_t b : n_bins) cfg.bins_max = std::max(cfg.bins_max, b);
@@ -126,6 +128,7 @@ int ilog2_ceil(int64_t v) {
 // the fastest for this problem shape.
 GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, aiwc_rf_forest* F,
                      const uint8_t* codes, int64_t n, const aiwc_rf_binner* binner, const double* y, int64_t* y_fp,
+                     uint8_t* codes_p,
                      const int32_t* d_train, uint32_t* queue, hipStream_t s) {
   const int64_t n_tasks = (int64_t)F->tasks.size();
   TuneKey key{device_info().cus, ilog2_ceil(base.n_cap), n_cols, base.bins_max, mtry_max, ilog2_ceil(n_tasks)};
@@ -133,7 +136,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
   if (tune_lookup(key, &best)) return best;
   const int64_t trial = std::min<int64_t>(n_tasks, 16LL * device_info().cus);
   launch_init(F->status.p, nullptr, s);
-  launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, F->status.p, s);
+  launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, codes_p, F->status.p, s);
   const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max);
   hipEvent_t e0, e1;
   AIWC_HIP(hipEventCreate(&e0));
@@ -149,7 +152,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
     DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
     launch_init(nullptr, queue, s);
     AIWC_HIP(hipEventRecord(e0, s));
-    launch_grow(c, codes, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial, F->nodes.p,
+    launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial, F->nodes.p,
                 F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p, base.n_cap, mtry_max, grid, s);
     AIWC_HIP(hipEventRecord(e1, s));
     AIWC_HIP(hipEventSynchronize(e1));
@@ -379,12 +382,13 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
       AIWC_HIP(hipMemcpyAsync(d_train.p, train_rows.data(), sizeof(int32_t) * train_rows.size(), hipMemcpyHostToDevice, s));
     F->inbag.reset((size_t)inbag_words, s);
     DevBuf<int64_t> y_fp((size_t)n, s);
+    DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte row reads
     DevBuf<uint32_t> queue(1, s);
 
     GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
     const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
     const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
-    if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p,
+    if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p,
                                                   d_train.p, queue.p, s);
 
     if (plain) {
@@ -398,8 +402,8 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         const int32_t nt = params_host[f].num_trees;
         const int grid = grow_grid_size(cfg, nt, mtry_max, n_cols);
         launch_init(nullptr, queue.p, s);
-        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
-        launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
+        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
+        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
                     F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, F->inbag.p, queue.p, F->status.p, scratch.p,
                     n_cap, mtry_max, grid, s);
       }
@@ -420,8 +424,8 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         AIWC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         try {
           launch_init(F->status.p, queue.p, cs);
-          launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, cs);
-          launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+          launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, cs);
+          launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
                       F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap,
                       mtry_max, grid, cs);
         } catch (...) {
@@ -444,9 +448,9 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
         (void)hipEventDestroy(ev);
       } else {
         launch_init(F->status.p, queue.p, s);
-        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p, s);
+        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
         AIWC_HIP(hipEventRecord(F->grow_begin, s));
-        launch_grow(cfg, codes, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
                     F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
                     grid, s);
         AIWC_HIP(hipEventRecord(F->grow_end, s));

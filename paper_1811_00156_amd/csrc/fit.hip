@@ -16,9 +16,11 @@
 //          each lane's split found from the segment's rows staged in LDS;
 //        - large (<= huge limit): one wave per (node, column), LDS histogram of
 //          (N, S, Q) per bin and a wave prefix scan over bins;
-//        - huge: the whole workgroup builds the LDS histograms of all candidate
-//          columns at once (each row's entry is read once), then one wave per
-//          column scans;
+//        - wide (above a tuned size): the whole workgroup takes a batch of such
+//          nodes at once; each row's entry is read once and its codes in all
+//          candidate columns are gathered by one thread, into packed (N, S)
+//          LDS histograms of every node and candidate column of the batch;
+//          one wave per (node, column) then scans;
 //      every split maximises S_L^2/N_L + S_R^2/N_R; ties keep the lowest
 //      (column, bin);
 //   3. split nodes get breadth-first child ids from a workgroup scan, node words
@@ -87,7 +89,7 @@ struct Scratch {
   uint32_t* curR;
   NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
   NodeDesc* big;
-  uint32_t* huge;
+  NodeDesc* huge;
   Rec* recs;  // large node j's candidate i at j * mtry + i
 };
 
@@ -126,7 +128,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   for (int c = 0; c < kSegClasses; ++c)
     s->seg[c] = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * (n / (1 + (c ? (2u << c) : 0)) + 1)));
   s->big = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
-  s->huge = reinterpret_cast<uint32_t*>(take(4 * n_large));
+  s->huge = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   return off;
 }
@@ -142,6 +144,8 @@ struct WaveHist {
 struct GrowArgs {
   const uint8_t* codes;
   int32_t C;
+  const uint8_t* codes_p;  // the same codes, rows padded to Cp (a multiple of 16) bytes
+  int32_t Cp;
   const int32_t* n_bins;
   const int64_t* y_fp;
   const int32_t* train_rows;
@@ -157,11 +161,11 @@ struct GrowArgs {
   uint8_t* scratch;
   int64_t n_cap;
   int32_t mtry_max;
-  int32_t huge_min;   // nodes with more rows than this use the workgroup-wide histogram
-  int32_t bstride;    // bins per column histogram in the workgroup-wide layout
-  int32_t huge_cols;  // columns whose histograms fit the LDS at once
+  int32_t huge_min;  // nodes with more rows than this are searched in workgroup-wide batches
+  int32_t bstride;   // bins per column histogram in the workgroup-wide layout
   size_t scratch_stride;
   uint32_t union_bytes;  // dynamic LDS
+  uint32_t wave_bytes;   // per-wave area of the split-search tasks
 };
 
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -257,6 +261,43 @@ struct Ctx {
 // columns a strictly greater score is needed, so ties keep the lowest column.
 // The segment's first lane then decides the node; the children's sums come
 // from one more segment reduction over the winning column.
+// Packed bin of the workgroup-wide and rank histograms: N * 2^45 + S in one unsigned
+// 64-bit word.  With N <= 2^18 and |S| <= 2^40 (the fixed-point budget) a bin,
+// and every prefix sum of bins, lies in [0, 2^64) and decodes exactly; a bin
+// is empty iff its word is 0.  One LDS atomic adds a row to a bin.
+__device__ __forceinline__ uint64_t pack_ns(uint32_t w, int64_t wy) { return ((uint64_t)w << 45) + (uint64_t)wy; }
+__device__ __forceinline__ uint32_t packed_n(uint64_t v) { return (uint32_t)((v + (1ull << 44)) >> 45); }
+__device__ __forceinline__ int64_t packed_s(uint64_t v, uint32_t n) { return (int64_t)(v - ((uint64_t)n << 45)); }
+
+// The children's sums of a small node from one segment reduction, written by
+// the segment's first lane with the decision.
+template <int W>
+__device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node_ok, int r, bool split, uint32_t col,
+                                             uint32_t bin, bool left, uint32_t w, int64_t wy, int64_t y) {
+  uint32_t NL = left ? w : 0u;
+  int64_t SL = left ? wy : 0;
+  uint64_t QL = left ? (uint64_t)(wy * y) : 0ull;
+#pragma unroll
+  for (int d = W / 2; d >= 1; d >>= 1) {
+    NL += (uint32_t)__shfl_xor((int)NL, d, W);
+    SL += __shfl_xor(SL, d, W);
+    QL += __shfl_xor(QL, d, W);
+  }
+  if (node_ok && r == 0) {
+    if (split) {
+      x.sc.dcol[k] = (uint8_t)col;
+      x.sc.dbin[k] = (uint8_t)bin;
+      x.sc.dNL[k] = NL;
+      x.sc.dSL[k] = SL;
+      x.sc.dQL[k] = QL;
+      x.sc.status[k] = kSplit;
+    } else {
+      x.sc.status[k] = kLeaf;
+    }
+  }
+  wave_lds_sync();
+}
+
 template <int W>
 __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
@@ -279,7 +320,6 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
   int64_t* s_wy = reinterpret_cast<int64_t*>(area);        // [64]
   uint32_t* s_w = reinterpret_cast<uint32_t*>(area + 512);  // [64]
-  uint8_t* s_codes = area + 1024;                           // [64 columns][64 lanes]
   s_wy[lane] = wy;
   s_w[lane] = w;
   const uint8_t* rowp = a.codes + (size_t)row * a.C;
@@ -287,6 +327,7 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
 
   double best = -1.0;
   uint32_t best_cb = 0xFFFFFFFFu;
+  uint8_t* s_codes = area + 1024;  // [64 columns][64 lanes]
   for (int i0 = 0; i0 < mtry; i0 += kWave) {
     const int nc = min(kWave, mtry - i0);
     // gather the row's codes in every candidate column of this chunk at once
@@ -327,32 +368,11 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
   const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
-  uint32_t NL = left ? w : 0u;
-  int64_t SL = left ? wy : 0;
-  uint64_t QL = left ? (uint64_t)(wy * y) : 0ull;
-#pragma unroll
-  for (int d = W / 2; d >= 1; d >>= 1) {
-    NL += (uint32_t)__shfl_xor((int)NL, d, W);
-    SL += __shfl_xor(SL, d, W);
-    QL += __shfl_xor(QL, d, W);
-  }
-  if (node_ok && r == 0) {
-    if (split) {
-      x.sc.dcol[k] = (uint8_t)col;
-      x.sc.dbin[k] = (uint8_t)bin;
-      x.sc.dNL[k] = NL;
-      x.sc.dSL[k] = SL;
-      x.sc.dQL[k] = QL;
-      x.sc.status[k] = kSplit;
-    } else {
-      x.sc.status[k] = kLeaf;
-    }
-  }
-  wave_lds_sync();
+  small_finish<W>(x, k, node_ok, r, split, col, bin, left, w, wy, y);
 }
 
 // Nodes of 33..64 rows: one node per wave, one row per lane.  Per candidate
-// column the rows' weights and sums are added into LDS bins of the codes that
+// column the rows' packed (w, w y) are added into LDS bins of the codes that
 // occur, the occurring codes are ranked through a 256-bit presence mask, and a
 // wave prefix scan over the ranked codes gives the left sums of every split
 // (cost independent of the bin count and of the number of rows).
@@ -369,35 +389,33 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
   const uint32_t w = valid ? entry_w(e) : 0u;
   const int64_t y = entry_y(e);
   const int64_t wy = (int64_t)w * y;
+  const uint64_t pv = pack_ns(w, wy);
   const uint8_t* rowp = a.codes + (size_t)entry_row(e) * a.C;
   const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
-  uint32_t* hN = reinterpret_cast<uint32_t*>(area);              // [256]
-  int64_t* hS = reinterpret_cast<int64_t*>(area + 1024);          // [256]
-  uint32_t* mask = reinterpret_cast<uint32_t*>(area + 3072);      // [8]
-  uint32_t* dN = reinterpret_cast<uint32_t*>(area + 3104);        // [64]
-  int64_t* dS = reinterpret_cast<int64_t*>(area + 3360);          // [64]
-  uint32_t* dC = reinterpret_cast<uint32_t*>(area + 3872);        // [64]
+  uint64_t* hv = reinterpret_cast<uint64_t*>(area);            // [256] packed bins by code
+  uint32_t* mask = reinterpret_cast<uint32_t*>(area + 2048);   // [8]
+  uint64_t* dV = reinterpret_cast<uint64_t*>(area + 2112);     // [64] bins by rank
+  uint32_t* dC = reinterpret_cast<uint32_t*>(area + 2624);     // [64] codes by rank
+  uint8_t* s_cand = area + 2880;                               // [mtry]
+  for (int i = lane; i < mtry; i += kWave) s_cand[i] = cand[i];
+  wave_lds_sync();
 
   double best = -1.0;
   uint32_t best_cb = 0xFFFFFFFFu;
-  uint32_t c_next = rfl(cand[0]);
+  uint32_t c_next = rfl(s_cand[0]);
   uint32_t code_next = valid ? rowp[c_next] : 0u;
   for (int i = 0; i < mtry; ++i) {
     const uint32_t c = c_next, code = code_next;
     if (i + 1 < mtry) {  // fetch the next column's codes while this one is scanned
-      c_next = rfl(cand[i + 1]);
+      c_next = rfl(s_cand[i + 1]);
       code_next = valid ? rowp[c_next] : 0u;
     }
-    if (valid) {
-      hN[code] = 0;
-      hS[code] = 0;
-    }
+    if (valid) hv[code] = 0;
     if (lane < 8) mask[lane] = 0;
     wave_lds_sync();
     if (valid) {
-      atomicAdd(&hN[code], w);
-      atomicAdd((unsigned long long*)&hS[code], (unsigned long long)wy);
+      atomicAdd((unsigned long long*)&hv[code], (unsigned long long)pv);
       atomicOr(&mask[code >> 5], 1u << (code & 31));
     }
     wave_lds_sync();
@@ -411,17 +429,16 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
     }
     below += (uint32_t)__popc(mask[code >> 5] & ((1u << (code & 31)) - 1u));
     if (valid) {
-      dN[below] = hN[code];
-      dS[below] = hS[code];
+      dV[below] = hv[code];
       dC[below] = code;
     }
     wave_lds_sync();
     const bool have = (uint32_t)lane < total;
-    const uint32_t n_i = have ? dN[lane] : 0u;
-    const int64_t s_i = have ? dS[lane] : 0;
+    const uint64_t v_i = have ? dV[lane] : 0ull;
     const uint32_t bin = have ? dC[lane] : 0xFFFFu;
-    const uint32_t NL = wave_incl_scan_u32(n_i);
-    const int64_t SL = wave_incl_scan<int64_t>(s_i);
+    const uint64_t V = wave_incl_scan<uint64_t>(v_i);
+    const uint32_t NL = packed_n(V);
+    const int64_t SL = packed_s(V, NL);
     double sc = -1.0;
     if ((uint32_t)lane + 1 < total) sc = split_score(SL, NL, S - SL, N - NL);
     const ArgMax am = wave_argmax(sc, (int32_t)bin);
@@ -493,6 +510,45 @@ __device__ __forceinline__ ArgMax scan_column(const uint32_t* hN, const uint64_t
         oNL = NL;
         oSL = SL;
         oQL = QL;
+      }
+    }
+  }
+  return wave_argmax(lbest, lbin);
+}
+
+// scan_column over packed bins (B <= 256, so a lane owns at most 4 bins).
+__device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_t N, int64_t S, uint32_t& oNL,
+                                              int64_t& oSL) {
+  const int lane = (int)lane_id();
+  const int R = (B + kWave - 1) / kWave;
+  const int b0 = lane * R;
+  uint64_t h[4];
+  uint64_t loc = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    h[u] = (u < R && b0 + u < B) ? hv[b0 + u] : 0ull;
+    loc += h[u];
+  }
+  uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
+  double lbest = -1.0;
+  int32_t lbin = INT_MAX;
+  oNL = 0;
+  oSL = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int b = b0 + u;
+    // an empty bin repeats the previous split, which already won any tie
+    if (h[u] == 0) continue;
+    v += h[u];
+    const uint32_t NL = packed_n(v);
+    if (b <= B - 2 && NL < N) {
+      const int64_t SL = packed_s(v, NL);
+      const double s = split_score(SL, NL, S - SL, N - NL);
+      if (s > lbest) {
+        lbest = s;
+        lbin = b;
+        oNL = NL;
+        oSL = SL;
       }
     }
   }
@@ -583,88 +639,182 @@ __device__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int 
   }
 }
 
+constexpr int kWideMax = 8;  // nodes per workgroup-wide batch
+
 struct Shared {
   uint32_t tmp[17];
   uint64_t red[16];
-  uint32_t cnt[3 + kSegClasses];  // [1] large, [2] huge, [3..] small nodes per segment width
+  uint32_t cnt[3 + kSegClasses];  // [1] large, [2] wide, [3..] small nodes per segment width
   uint32_t task;
-  uint8_t cand[256];
-  Rec recs[256];
+  // the wide batch being searched: node j's level index, first entry, rows,
+  // first chunk, weight, sum, left-side sum of squares, and decision
+  uint32_t wk[kWideMax], wstart[kWideMax], wlen[kWideMax], wcpre[kWideMax], wN[kWideMax];
+  int64_t wS[kWideMax];
+  uint64_t wql[kWideMax];
+  uint32_t wcol[kWideMax], wbin[kWideMax];
+  alignas(8) uint8_t cand[256];  // wide node j's candidate i at j * round_up(mtry, 8) + i
+  Rec recs[256];      // node j's record of candidate i at j * mtry + i
 };
 
-// Huge node: every thread adds its rows into the histograms of up to
-// huge_cols candidate columns at once (all mtry in one pass when they fit);
-// one wave per column then scans.
+// A batch of nb wide nodes.  Node j's rows are cut into chunks of 64, one
+// wave per chunk, so the candidate columns are uniform across a wave.  Each
+// lane reads its row's entry once and, when the padded code rows fit 80 bytes,
+// the whole code row with five 16-byte loads; the candidate codes are then
+// picked from registers and each is added to the packed bin of its (node,
+// column) histogram (hc columns at a time when they do not all fit the LDS).
+// One wave per (node, column) then scans, the nodes are decided from the
+// per-column records, and a last pass over the chunks sums w y^2 over each
+// split node's left side.
 template <int BLOCK>
-__device__ void huge_node(const Ctx& x, uint32_t k, uint8_t* lds, Shared& sh) {
+__device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, uint8_t* lds, Shared& sh) {
   constexpr int NW = BLOCK / kWave;
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
-  const int bs = a.bstride, hc = a.huge_cols;
+  const int bs = a.bstride;
   const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
-  uint32_t* hN = reinterpret_cast<uint32_t*>(lds);
-  uint64_t* hS = reinterpret_cast<uint64_t*>(lds + (size_t)4 * hc * bs);
-  uint64_t* hQ = hS + (size_t)hc * bs;
-  for (int i = tid; i < mtry; i += BLOCK) sh.cand[i] = x.sc.cand[(size_t)k * mtry + i];
-  const uint32_t start = x.mstart[k], end = x.mend[k];
-  const uint32_t N = x.mN[k];
-  const int64_t S = x.mS[k];
+  uint64_t* H = reinterpret_cast<uint64_t*>(lds);
+  uint32_t cpre[kWideMax];  // first chunk of node j (uniform)
+  uint32_t n_chunks = 0;
+#pragma unroll
+  for (int j = 0; j < kWideMax; ++j) {
+    cpre[j] = n_chunks;
+    n_chunks += j < nb ? (list[j].len + kWave - 1) / kWave : 0u;
+  }
+  if (tid < nb) {
+    const NodeDesc d = list[tid];
+    sh.wk[tid] = d.k;
+    sh.wstart[tid] = d.start;
+    sh.wlen[tid] = d.len;
+    sh.wN[tid] = d.N;
+    sh.wS[tid] = d.S;
+    sh.wql[tid] = 0;
+#pragma unroll
+    for (int j = 0; j < kWideMax; ++j)
+      if (j == tid) sh.wcpre[j] = cpre[j];
+  }
+  // candidates padded to 8 per node (with the node's last one), read 8 at a time
+  const int cst = (mtry + 7) & ~7;
+  for (int i = tid; i < nb * cst; i += BLOCK)
+    sh.cand[i] = x.sc.cand[(size_t)list[i / cst].k * mtry + min(i % cst, mtry - 1)];
+  __syncthreads();
+  // node of chunk ch: the number of later nodes' first chunks <= ch
+  auto node_of = [&](uint32_t ch) {
+    int j = 0;
+#pragma unroll
+    for (int jj = 1; jj < kWideMax; ++jj) j += (jj < nb && ch >= cpre[jj]) ? 1 : 0;
+    return j;
+  };
+  const bool row_regs = a.Cp <= 80;
   for (int c0 = 0; c0 < mtry; c0 += hc) {
     const int nc = min(hc, mtry - c0);
-    for (int i = tid; i < nc * bs; i += BLOCK) {
-      hN[i] = 0;
-      hS[i] = 0;
-      hQ[i] = 0;
-    }
+    const int words = nb * nc * bs;
+    for (int i = 2 * tid; i < words; i += 2 * BLOCK) *reinterpret_cast<uint4*>(H + i) = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    for (uint32_t p = start + tid; p < end; p += BLOCK) {
-      const uint64_t e = x.buf[p];
-      const uint32_t w = entry_w(e);
-      const int64_t y = entry_y(e);
-      const int64_t wy = (int64_t)w * y;
-      const uint64_t wyy = (uint64_t)(wy * y);
-      const uint8_t* rp = a.codes + (size_t)entry_row(e) * a.C;
-      // the row's codes in eight candidate columns are fetched together
-      for (int i0 = 0; i0 < nc; i0 += 8) {
-        uint32_t cd[8];
+    for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
+      const int j = node_of(ch);
+      const uint32_t r = (ch - sh.wcpre[j]) * kWave + (uint32_t)lane;
+      const bool valid = r < sh.wlen[j];
+      uint64_t v = 0;
+      uint32_t row = 0;
+      if (valid) {
+        const uint64_t e = x.buf[sh.wstart[j] + r];
+        const uint32_t w = entry_w(e);
+        v = pack_ns(w, (int64_t)w * entry_y(e));
+        row = entry_row(e);
+      }
+      const uint8_t* cj = sh.cand + j * cst + c0;
+      uint64_t* Hj = H + (size_t)j * nc * bs;
+      if (row_regs) {
+        // five unconditional loads: the padded copy has 64 bytes of slack after
+        // its last row, and a lane without a row reads row 0
+        uint32_t rw[20];
+        const uint4* rp = reinterpret_cast<const uint4*>(a.codes_p + (size_t)row * a.Cp);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cd[u] = i0 + u < nc ? rp[sh.cand[c0 + i0 + u]] : 0u;
+        for (int u = 0; u < 5; ++u) {
+          const uint4 t = rp[u];
+          rw[4 * u] = t.x;
+          rw[4 * u + 1] = t.y;
+          rw[4 * u + 2] = t.z;
+          rw[4 * u + 3] = t.w;
+        }
+        for (int i0 = 0; i0 < nc; i0 += 8) {
+          const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
+          const uint32_t lo = rfl((uint32_t)c8), hi = rfl((uint32_t)(c8 >> 32));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (i0 + u < nc) {
-            const int h = (i0 + u) * bs + (int)cd[u];
-            atomicAdd(&hN[h], w);
-            atomicAdd((unsigned long long*)&hS[h], (unsigned long long)wy);
-            atomicAdd((unsigned long long*)&hQ[h], (unsigned long long)wyy);
+          for (int u = 0; u < 8; ++u) {
+            const uint32_t col = ((u < 4 ? lo : hi) >> (8 * (u & 3))) & 0xFFu;
+            const uint32_t code = (rw[col >> 2] >> (8 * (col & 3))) & 0xFFu;
+            if (valid && i0 + u < nc)
+              atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)code], (unsigned long long)v);
           }
+        }
+      } else {
+        const uint8_t* rp = a.codes + (size_t)row * a.C;
+        for (int i0 = 0; i0 < nc; i0 += 8) {
+          const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
+          uint32_t cd[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) cd[u] = valid ? rp[(uint32_t)(c8 >> (8 * u)) & 0xFFu] : 0u;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (valid && i0 + u < nc)
+              atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)cd[u]], (unsigned long long)v);
         }
       }
     }
     __syncthreads();
-    for (int i = wid; i < nc; i += NW) {
-      const int c = sh.cand[c0 + i];
-      const int B = a.n_bins[c];
+    for (int t = wid; t < nb * nc; t += NW) {
+      const int j = t / nc, i = t % nc;
+      const int c = sh.cand[j * cst + c0 + i];
       uint32_t NL;
       int64_t SL;
-      uint64_t QL;
-      const ArgMax am = scan_column(hN + i * bs, hS + i * bs, hQ + i * bs, B, N, S, NL, SL, QL);
+      const ArgMax am = scan_packed(H + (size_t)t * bs, a.n_bins[c], sh.wN[j], sh.wS[j], NL, SL);
       if (lane == am.lane) {
         Rec r;
         r.score = am.score;
         r.SL = SL;
-        r.QL = QL;
+        r.QL = 0;
         r.NL = NL;
         r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
-        sh.recs[c0 + i] = r;
+        sh.recs[j * mtry + c0 + i] = r;
       }
     }
     __syncthreads();
   }
-  if (tid == 0) decide_from_recs(x, k, sh.recs, mtry);
+  if (tid < nb) {
+    const uint32_t k = sh.wk[tid];
+    decide_from_recs(x, k, sh.recs + tid * mtry, mtry);
+    const bool split = x.sc.status[k] == kSplit;
+    sh.wcol[tid] = split ? x.sc.dcol[k] : kLeafCol;
+    sh.wbin[tid] = split ? x.sc.dbin[k] : 0u;
+  }
+  __syncthreads();
+  // left-side sum of w y^2 of every split node of the batch, chunk by chunk
+  for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
+    const int j = node_of(ch);
+    const uint32_t col = sh.wcol[j];
+    if (col == kLeafCol) continue;
+    const uint32_t r = (ch - sh.wcpre[j]) * kWave + (uint32_t)lane;
+    uint64_t val = 0;
+    if (r < sh.wlen[j]) {
+      const uint64_t e = x.buf[sh.wstart[j] + r];
+      if (a.codes_p[(size_t)entry_row(e) * a.Cp + col] <= sh.wbin[j]) {
+        const int64_t y = entry_y(e);
+        val = (uint64_t)((int64_t)entry_w(e) * y * y);
+      }
+    }
+    const uint64_t t = wave_sum(val);
+    if (lane == 0 && t != 0) atomicAdd((unsigned long long*)&sh.wql[j], (unsigned long long)t);
+  }
+  __syncthreads();
+  if (tid < nb && sh.wcol[tid] != kLeafCol) x.sc.dQL[sh.wk[tid]] = sh.wql[tid];
   __syncthreads();
 }
 
-template <int BLOCK>
+// WIDE: the launch may hold nodes above the wide limit (the kernel without
+// the wide-batch phase is compiled separately, so that small training sets
+// keep its leaner register allocation).
+template <int BLOCK, bool WIDE>
 __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, uint8_t* lds,
                           Shared& sh) {
   constexpr int NW = BLOCK / kWave;
@@ -760,19 +910,28 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
                            : cls == 3 ? sc.seg[3]
                                       : sc.seg[4];
           list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
-        } else if ((int32_t)len <= a.huge_min) {
+        } else if (!WIDE || (int32_t)len <= a.huge_min) {
           sc.status[k] = kBig;
           sc.big[atomicAdd(&sh.cnt[1], 1u)] = NodeDesc{k, st, len, N, S};
         } else {
           sc.status[k] = kHuge;
-          sc.huge[atomicAdd(&sh.cnt[2], 1u)] = k;
+          sc.huge[atomicAdd(&sh.cnt[2], 1u)] = NodeDesc{k, st, len, N, S};
         }
       }
     }
     __syncthreads();
     const uint32_t n_big = sh.cnt[1], n_huge = sh.cnt[2];
-    // (b) huge nodes, one after another, with the whole workgroup
-    for (uint32_t h = 0; h < n_huge; ++h) huge_node<BLOCK>(x, sc.huge[h], lds, sh);
+    // (b) wide nodes, in batches, with the whole workgroup
+    if (WIDE && n_huge > 0) {
+      const int per_node = mtry * a.bstride * 8;
+      int nb = 1, hc = mtry;
+      if (per_node <= (int)a.union_bytes)
+        nb = min(min(kWideMax, 256 / ((mtry + 7) & ~7)), (int)a.union_bytes / per_node);
+      else  // column chunks of a multiple of 8 (the LDS holds at least 8 columns)
+        hc = max(8, (int)a.union_bytes / (a.bstride * 8) / 8 * 8);
+      for (uint32_t h0 = 0; h0 < n_huge; h0 += (uint32_t)nb)
+        wide_batch<BLOCK>(x, sc.huge + h0, (int)min((uint32_t)nb, n_huge - h0), hc, lds, sh);
+    }
     // (c) large-node columns and small-node segments, one wave each
     {
       const uint32_t n_big_tasks = n_big * (uint32_t)mtry;
@@ -782,7 +941,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         const uint32_t per_wave = (uint32_t)(kWave >> (2 + c));
         first[c + 1] = first[c] + (sh.cnt[3 + c] + per_wave - 1) / per_wave;
       }
-      WaveHist& wl = reinterpret_cast<WaveHist*>(lds)[wid];
+      WaveHist& wl = *reinterpret_cast<WaveHist*>(lds + (size_t)wid * a.wave_bytes);
       for (uint32_t t = wid; t < first[kSegClasses]; t += NW) {
         if (t < n_big_tasks)
           big_task(x, t / mtry, (int)(t % mtry), wl);
@@ -923,7 +1082,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
 
 // At most 128 VGPRs (four waves per SIMD): the persistent kernel is bound by
 // latency, so resident waves matter more than the few registers it spills.
-template <int BLOCK>
+template <int BLOCK, bool WIDE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_grow(GrowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ Shared sh;
@@ -936,7 +1095,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     __syncthreads();
     if (t >= (uint32_t)a.n_tasks) return;
     const TreeTask T = a.tasks[t];
-    grow_tree<BLOCK>(a, T, (int32_t)t, sc, lds, sh);
+    grow_tree<BLOCK, WIDE>(a, T, (int32_t)t, sc, lds, sh);
     __syncthreads();
   }
 }
@@ -950,7 +1109,7 @@ __global__ void k_init(uint32_t* status, uint32_t* queue) {
 
 // y -> y_fp = rint(y * 2^16) with range check, and every code < its column's bin count.
 __global__ void k_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* n_bins, const double* y,
-                          int64_t* y_fp, uint32_t* status) {
+                          int64_t* y_fp, uint8_t* codes_p, int32_t Cp, uint32_t* status) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t bad = 0;
@@ -966,6 +1125,13 @@ __global__ void k_prepare(const uint8_t* codes, int64_t n, int32_t C, const int3
   const int64_t total = n * C;
   for (int64_t i = g; i < total; i += stride)
     if ((int32_t)codes[i] >= n_bins[i % C]) bad |= kStatusBadCode;
+  // the padded copy: row i at i * Cp, zeros after column C - 1
+  const int64_t total_p = n * Cp;
+  for (int64_t i = g; i < total_p; i += stride) {
+    const int64_t row = i / Cp;
+    const int32_t c = (int32_t)(i - row * Cp);
+    codes_p[i] = c < C ? codes[row * C + c] : 0u;
+  }
   if (bad) atomicOr(status, bad);
 }
 
@@ -973,38 +1139,44 @@ __global__ void k_set_i32(int32_t* p, int32_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-// Dynamic LDS of the grow kernel: the per-wave histograms, or the histograms of
-// a huge node's candidate columns, or the candidate-draw rows, whichever is
+// Dynamic LDS of the grow kernel: the per-wave histograms, or the packed
+// histograms of a batch of wide nodes, or the candidate-draw rows, whichever is
 // largest (the three are used in different phases of a level).
 struct Layout {
   uint32_t union_bytes;
+  uint32_t wave_bytes;
   int32_t bstride;
-  int32_t huge_cols;
 };
+
+// A launch has wide nodes iff a tree's training set exceeds the wide limit.
+bool wide_launch(const GrowConfig& cfg) { return cfg.n_cap > cfg.huge_min; }
 
 Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   Layout L;
   L.bstride = (std::max(cfg.bins_max, 1) + 63) / 64 * 64;
-  const size_t waves = (size_t)(cfg.block / kWave) * sizeof(WaveHist);
+  // a wave's histogram, or the staging of its small-node task (the rank task's
+  // bins and candidates take 2880 + mtry bytes)
+  const size_t wb = std::max(sizeof(WaveHist), (size_t)2880 + (size_t)mtry_max);
+  L.wave_bytes = (uint32_t)((wb + 255) / 256 * 256);
+  const size_t waves = (size_t)(cfg.block / kWave) * L.wave_bytes;
   const size_t draw = (size_t)std::min(cfg.block, 256) * (size_t)C;
-  const size_t col_bytes = (size_t)L.bstride * (4 + 8 + 8);
-  size_t huge = 0;
-  if (cfg.n_cap > cfg.huge_min) {
-    const size_t cap = std::max<size_t>(waves, 96 * 1024);
-    const size_t cols = std::max<size_t>(1, std::min<size_t>((size_t)mtry_max, cap / col_bytes));
-    huge = cols * col_bytes;
+  size_t wide = 0;
+  if (wide_launch(cfg)) {
+    // by default a quarter of the 128 KiB per 256 threads, so that the
+    // workgroups that fit a CU still do
+    const size_t want = cfg.wide_bytes > 0 ? (size_t)cfg.wide_bytes : (size_t)cfg.block * 128;
+    wide = std::max(std::max(waves, want), (size_t)8 * L.bstride * 8);
   }
-  L.union_bytes = (uint32_t)std::max(std::max(waves, huge), draw);
-  L.huge_cols = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)mtry_max, L.union_bytes / col_bytes));
+  L.union_bytes = (uint32_t)std::max(std::max(waves, wide), draw);
   return L;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool WIDE>
 int occupancy(uint32_t lds) {
   int nb = 0;
-  AIWC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_grow<BLOCK>),
+  AIWC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_grow<BLOCK, WIDE>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grow<BLOCK>, BLOCK, lds));
+  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grow<BLOCK, WIDE>, BLOCK, lds));
   return nb;
 }
 
@@ -1026,10 +1198,10 @@ size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max) {
 }
 
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
-                    int64_t* y_fp, uint32_t* d_status, hipStream_t s) {
-  const int64_t work = n * C;
+                    int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s) {
+  const int64_t work = n * padded_cols(C);
   const int blocks = (int)std::min<int64_t>(2048, (work + 255) / 256);
-  k_prepare<<<std::max(blocks, 1), 256, 0, s>>>(codes, n, C, d_n_bins, y, y_fp, d_status);
+  k_prepare<<<std::max(blocks, 1), 256, 0, s>>>(codes, n, C, d_n_bins, y, y_fp, codes_p, padded_cols(C), d_status);
   AIWC_HIP(hipGetLastError());
 }
 
@@ -1037,10 +1209,11 @@ int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int
   const uint32_t lds = grow_layout(cfg, mtry_max, C).union_bytes;
   if (lds > device_info().lds_per_block) fail(AIWC_RF_EINVAL, "grow kernel LDS exceeds the device limit");
   int per_cu = 1;
+  const bool wide = wide_launch(cfg);
   switch (cfg.block) {
-    case 256: per_cu = occupancy<256>(lds); break;
-    case 512: per_cu = occupancy<512>(lds); break;
-    case 1024: per_cu = occupancy<1024>(lds); break;
+    case 256: per_cu = wide ? occupancy<256, true>(lds) : occupancy<256, false>(lds); break;
+    case 512: per_cu = wide ? occupancy<512, true>(lds) : occupancy<512, false>(lds); break;
+    case 1024: per_cu = wide ? occupancy<1024, true>(lds) : occupancy<1024, false>(lds); break;
     default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
   }
   if (per_cu < 1) fail(AIWC_RF_ENOMEM, "grow kernel does not fit the device (LDS or registers)");
@@ -1049,7 +1222,7 @@ int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int
   return (int)std::max<int64_t>(1, std::min<int64_t>(slots, n_tasks));
 }
 
-void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
+void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* codes_p, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
                  uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
                  uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,
@@ -1057,6 +1230,8 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const i
   GrowArgs a;
   a.codes = codes;
   a.C = C;
+  a.codes_p = codes_p;
+  a.Cp = padded_cols(C);
   a.n_bins = d_n_bins;
   a.y_fp = y_fp;
   a.train_rows = train_rows;
@@ -1076,12 +1251,28 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const i
   a.scratch_stride = grow_scratch_bytes(n_cap, mtry_max);
   const Layout L = grow_layout(cfg, mtry_max, C);
   a.union_bytes = L.union_bytes;
+  a.wave_bytes = L.wave_bytes;
   a.bstride = L.bstride;
-  a.huge_cols = L.huge_cols;
+  const bool wide = wide_launch(cfg);
   switch (cfg.block) {
-    case 256: k_grow<256><<<grid, 256, a.union_bytes, s>>>(a); break;
-    case 512: k_grow<512><<<grid, 512, a.union_bytes, s>>>(a); break;
-    case 1024: k_grow<1024><<<grid, 1024, a.union_bytes, s>>>(a); break;
+    case 256:
+      if (wide)
+        k_grow<256, true><<<grid, 256, a.union_bytes, s>>>(a);
+      else
+        k_grow<256, false><<<grid, 256, a.union_bytes, s>>>(a);
+      break;
+    case 512:
+      if (wide)
+        k_grow<512, true><<<grid, 512, a.union_bytes, s>>>(a);
+      else
+        k_grow<512, false><<<grid, 512, a.union_bytes, s>>>(a);
+      break;
+    case 1024:
+      if (wide)
+        k_grow<1024, true><<<grid, 1024, a.union_bytes, s>>>(a);
+      else
+        k_grow<1024, false><<<grid, 1024, a.union_bytes, s>>>(a);
+      break;
     default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
   }
   AIWC_HIP(hipGetLastError());

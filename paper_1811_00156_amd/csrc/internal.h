@@ -152,7 +152,8 @@ void launch_bin_encode(const float* X, const int32_t* dev, int64_t n, int32_t p,
 struct GrowConfig {
   int block = 512;       // threads per workgroup
   int wg_per_cu = 0;     // 0 = as many as occupancy allows
-  int huge_min = 4096;   // nodes with more in-bag rows use the workgroup-wide histogram
+  int huge_min = 4096;   // nodes with more in-bag rows are searched in workgroup-wide batches
+  int wide_bytes = 0;    // LDS of a wide batch's histograms (0: 128 bytes per thread)
   int bins_max = 256;    // largest bin count of any column
   int64_t n_cap = 0;     // largest training set of any tree
 };
@@ -174,11 +175,15 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base);
 
 void launch_init(uint32_t* d_status, uint32_t* d_queue, hipStream_t s);  // either may be null
 void launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
+// Validates y and the codes, writes y_fp and a copy of the codes whose rows are
+// padded to padded_cols(C) bytes (16-byte aligned rows); the copy's buffer must
+// hold 64 bytes more than n * padded_cols(C), read but never used.
+inline int32_t padded_cols(int32_t C) { return (C + 15) / 16 * 16; }
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
-                    int64_t* y_fp, uint32_t* d_status, hipStream_t s);
+                    int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s);
 size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
-void launch_grow(const GrowConfig& cfg, const uint8_t* codes, int32_t C, const int32_t* d_n_bins,
+void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* codes_p, int32_t C, const int32_t* d_n_bins,
                  const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
                  uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
                  uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,

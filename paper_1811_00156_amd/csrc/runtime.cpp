@@ -214,18 +214,18 @@ void tune_store(const TuneKey& key, const GrowConfig& cfg) {
 }
 
 std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
+  // workgroup size x wide-node limit; a limit at or above the largest training
+  // set means no wide nodes, which is timed once per workgroup size
   std::vector<GrowConfig> out;
   for (int block : {256, 512, 1024}) {
-    if (base.n_cap > 2048) {
-      for (int h : {2048, 4096, 8192}) {
-        GrowConfig c = base;
-        c.block = block;
-        c.huge_min = h;
-        out.push_back(c);
-      }
-    } else {
+    bool narrow_done = false;
+    for (int h : {64, 512, 4096}) {
+      const bool narrow = base.n_cap <= h;
+      if (narrow && narrow_done) continue;
+      narrow_done = narrow_done || narrow;
       GrowConfig c = base;
       c.block = block;
+      c.huge_min = h;
       out.push_back(c);
     }
   }

@@ -41,7 +41,7 @@ def fit_with(rf, ds, ob, env, flags=0):
 
 
 @pytest.mark.parametrize("block", ["256", "512", "1024"])
-@pytest.mark.parametrize("huge_min", ["2048", "4096", "100000"])
+@pytest.mark.parametrize("huge_min", ["64", "300", "2048", "4096", "100000"])
 def test_shape_invariance(setup, block, huge_min):
     rf, ds, ob, of = setup
     log(f"shape block={block} huge_min={huge_min}")
@@ -60,3 +60,34 @@ def test_autotuned_fit_matches(setup):
     codes = to_dev(ob.codes)
     _, yhat = __import__("oracle.oracle", fromlist=["predict"]).predict(of, ob.codes)
     assert np.array_equal(rf.aiwc_rf_predict(f, codes).cpu().numpy().view(np.uint64), yhat.view(np.uint64))
+
+
+@pytest.mark.parametrize("block", ["256", "1024"])
+def test_wide_batches_in_column_chunks(block):
+    """Every node above 64 rows in workgroup-wide batches, with more candidate
+    columns (35 of 35, 256 bins) than one batch's LDS holds at a 256-thread
+    workgroup, so the columns are histogrammed in chunks."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    log(f"wide chunks block={block}")
+    ds = synth.d1()
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 256)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 4, 35, 1, seed=5)
+    old = {k: os.environ.get(k) for k in ("AIWC_RF_GROW_BLOCK", "AIWC_RF_HUGE_MIN")}
+    os.environ.update({"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": "64"})
+    try:
+        f = rf.aiwc_rf_fit(to_dev(ob.codes), rf.aiwc_rf_binner_from_counts(ob.n_bins), to_dev(ds.y),
+                           rf.make_params(4, 35, 1, True, 5))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"wide chunks block {block} tree {t}")
