@@ -56,7 +56,6 @@ struct NodeDesc {
 struct Rec {
   double score;
   int64_t SL;
-  uint64_t QL;
   uint32_t NL;
   uint32_t colbin;  // column << 8 | bin
 };
@@ -83,7 +82,7 @@ struct Scratch {
   uint8_t* dbin;
   uint32_t* dNL;
   int64_t* dSL;
-  uint64_t* dQL;
+  uint64_t* qacc;  // split node k's left-side sum of w y^2, added up by the partition
   uint32_t* rank;
   uint32_t* curL;
   uint32_t* curR;
@@ -120,7 +119,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->dbin = reinterpret_cast<uint8_t*>(take(n));
   s->dNL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->dSL = reinterpret_cast<int64_t*>(take(8 * n));
-  s->dQL = reinterpret_cast<uint64_t*>(take(8 * n));
+  s->qacc = reinterpret_cast<uint64_t*>(take(8 * n));
   s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
@@ -133,12 +132,12 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   return off;
 }
 
-// Per-wave LDS: one histogram of (N, S, Q) over at most 256 bins.  The small
-// node method reuses it for the segment's staged rows and codes.
+// Per-wave LDS: one histogram of packed (N, S) bins over at most 256 bins.
+// The small-node methods reuse the area for their staged weights, sums and
+// codes (up to 4864 bytes).
 struct WaveHist {
-  uint32_t hN[kMaxBins];
-  uint64_t hS[kMaxBins];
-  uint64_t hQ[kMaxBins];
+  uint64_t hv[kMaxBins];
+  uint8_t stage[4864 - 8 * kMaxBins];
 };
 
 struct GrowArgs {
@@ -269,19 +268,17 @@ __device__ __forceinline__ uint64_t pack_ns(uint32_t w, int64_t wy) { return ((u
 __device__ __forceinline__ uint32_t packed_n(uint64_t v) { return (uint32_t)((v + (1ull << 44)) >> 45); }
 __device__ __forceinline__ int64_t packed_s(uint64_t v, uint32_t n) { return (int64_t)(v - ((uint64_t)n << 45)); }
 
-// The children's sums of a small node from one segment reduction, written by
-// the segment's first lane with the decision.
+// The left child's weight and sum of a small node from one segment
+// reduction, written by the segment's first lane with the decision.
 template <int W>
 __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node_ok, int r, bool split, uint32_t col,
-                                             uint32_t bin, bool left, uint32_t w, int64_t wy, int64_t y) {
+                                             uint32_t bin, bool left, uint32_t w, int64_t wy) {
   uint32_t NL = left ? w : 0u;
   int64_t SL = left ? wy : 0;
-  uint64_t QL = left ? (uint64_t)(wy * y) : 0ull;
 #pragma unroll
   for (int d = W / 2; d >= 1; d >>= 1) {
     NL += (uint32_t)__shfl_xor((int)NL, d, W);
     SL += __shfl_xor(SL, d, W);
-    QL += __shfl_xor(QL, d, W);
   }
   if (node_ok && r == 0) {
     if (split) {
@@ -289,7 +286,6 @@ __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node
       x.sc.dbin[k] = (uint8_t)bin;
       x.sc.dNL[k] = NL;
       x.sc.dSL[k] = SL;
-      x.sc.dQL[k] = QL;
       x.sc.status[k] = kSplit;
     } else {
       x.sc.status[k] = kLeaf;
@@ -368,7 +364,7 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
   const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
-  small_finish<W>(x, k, node_ok, r, split, col, bin, left, w, wy, y);
+  small_finish<W>(x, k, node_ok, r, split, col, bin, left, w, wy);
 }
 
 // Nodes of 33..64 rows: one node per wave, one row per lane.  Per candidate
@@ -453,14 +449,12 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
   const bool left = split && valid && rowp[col] <= bin;
   const uint32_t NL = wave_sum(left ? w : 0u);
   const int64_t SL = wave_sum(left ? wy : (int64_t)0);
-  const uint64_t QL = wave_sum(left ? (uint64_t)(wy * y) : 0ull);
   if (lane == 0) {
     if (split) {
       x.sc.dcol[k] = (uint8_t)col;
       x.sc.dbin[k] = (uint8_t)bin;
       x.sc.dNL[k] = NL;
       x.sc.dSL[k] = SL;
-      x.sc.dQL[k] = QL;
       x.sc.status[k] = kSplit;
     } else {
       x.sc.status[k] = kLeaf;
@@ -469,64 +463,19 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
   wave_lds_sync();
 }
 
-// Scan one column's histogram (B bins) with a wave: lane l owns bins
-// [l R, (l+1) R); prefix sums give the left side of every split b <= B-2.
-// Returns the wave's best (max score, lowest bin) in every lane; the left
-// sums oNL, oSL, oQL of that split are valid in lane `am.lane`.
-__device__ __forceinline__ ArgMax scan_column(const uint32_t* hN, const uint64_t* hS, const uint64_t* hQ, int B,
-                                              uint32_t N, int64_t S, uint32_t& oNL, int64_t& oSL, uint64_t& oQL) {
-  const int lane = (int)lane_id();
-  const int R = (B + kWave - 1) / kWave;
-  const int b0 = lane * R;
-  const int b1 = min(b0 + R, B);
-  uint32_t n_loc = 0;
-  int64_t s_loc = 0;
-  uint64_t q_loc = 0;
-  for (int b = b0; b < b1; ++b) {
-    n_loc += hN[b];
-    s_loc += (int64_t)hS[b];
-    q_loc += hQ[b];
-  }
-  uint32_t NL = wave_incl_scan_u32(n_loc) - n_loc;
-  int64_t SL = wave_incl_scan<int64_t>(s_loc) - s_loc;
-  uint64_t QL = wave_incl_scan<uint64_t>(q_loc) - q_loc;
-  double lbest = -1.0;
-  int32_t lbin = INT_MAX;
-  oNL = 0;
-  oSL = 0;
-  oQL = 0;
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t hn = hN[b];
-    // an empty bin repeats the previous split, which already won any tie
-    if (hn == 0) continue;
-    NL += hn;
-    SL += (int64_t)hS[b];
-    QL += hQ[b];
-    if (b <= B - 2 && NL < N) {
-      const double s = split_score(SL, NL, S - SL, N - NL);
-      if (s > lbest) {
-        lbest = s;
-        lbin = b;
-        oNL = NL;
-        oSL = SL;
-        oQL = QL;
-      }
-    }
-  }
-  return wave_argmax(lbest, lbin);
-}
-
-// scan_column over packed bins (B <= 256, so a lane owns at most 4 bins).
+// Scan one column's histogram of packed bins (B <= 256 bins) with a wave: lane
+// l owns bins [4l, 4l + 4); prefix sums give the left side of every split
+// b <= B-2.  Returns the wave's best (max score, lowest bin) in every lane; the
+// left sums oNL, oSL of that split are valid in lane `am.lane`.
 __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_t N, int64_t S, uint32_t& oNL,
                                               int64_t& oSL) {
   const int lane = (int)lane_id();
-  const int R = (B + kWave - 1) / kWave;
-  const int b0 = lane * R;
+  const int b0 = lane * 4;
   uint64_t h[4];
   uint64_t loc = 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    h[u] = (u < R && b0 + u < B) ? hv[b0 + u] : 0ull;
+    h[u] = b0 + u < B ? hv[b0 + u] : 0ull;
     loc += h[u];
   }
   uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
@@ -568,11 +517,7 @@ __device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
   const int64_t S = d.S;
   const int c = (int)rfl(x.sc.cand[(size_t)k * mtry + ci]);
   const int B = a.n_bins[c];
-  for (int b = lane; b < B; b += kWave) {
-    L.hN[b] = 0;
-    L.hS[b] = 0;
-    L.hQ[b] = 0;
-  }
+  for (int b = lane; b < B; b += kWave) L.hv[b] = 0;
   wave_lds_sync();
   // four rows per lane in flight: entries, then codes, then the atomics
   constexpr int U = 4;
@@ -587,24 +532,18 @@ __device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
     for (int u = 0; u < U; ++u) {
       if (p0 + u * kWave < end) {
         const uint32_t w = entry_w(e[u]);
-        const int64_t y = entry_y(e[u]);
-        const int64_t wy = (int64_t)w * y;
-        atomicAdd(&L.hN[code[u]], w);
-        atomicAdd((unsigned long long*)&L.hS[code[u]], (unsigned long long)wy);
-        atomicAdd((unsigned long long*)&L.hQ[code[u]], (unsigned long long)(wy * y));
+        atomicAdd((unsigned long long*)&L.hv[code[u]], (unsigned long long)pack_ns(w, (int64_t)w * entry_y(e[u])));
       }
     }
   }
   wave_lds_sync();
   uint32_t NL;
   int64_t SL;
-  uint64_t QL;
-  const ArgMax am = scan_column(L.hN, L.hS, L.hQ, B, N, S, NL, SL, QL);
+  const ArgMax am = scan_packed(L.hv, B, N, S, NL, SL);
   if (lane == am.lane) {
     Rec r;
     r.score = am.score;
     r.SL = SL;
-    r.QL = QL;
     r.NL = NL;
     r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
     x.sc.recs[(size_t)j * mtry + ci] = r;
@@ -632,7 +571,6 @@ __device__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int 
     x.sc.dbin[k] = (uint8_t)(r.colbin & 0xFF);
     x.sc.dNL[k] = r.NL;
     x.sc.dSL[k] = r.SL;
-    x.sc.dQL[k] = r.QL;
     x.sc.status[k] = kSplit;
   } else {
     x.sc.status[k] = kLeaf;
@@ -647,11 +585,9 @@ struct Shared {
   uint32_t cnt[3 + kSegClasses];  // [1] large, [2] wide, [3..] small nodes per segment width
   uint32_t task;
   // the wide batch being searched: node j's level index, first entry, rows,
-  // first chunk, weight, sum, left-side sum of squares, and decision
+  // first chunk, weight and sum
   uint32_t wk[kWideMax], wstart[kWideMax], wlen[kWideMax], wcpre[kWideMax], wN[kWideMax];
   int64_t wS[kWideMax];
-  uint64_t wql[kWideMax];
-  uint32_t wcol[kWideMax], wbin[kWideMax];
   alignas(8) uint8_t cand[256];  // wide node j's candidate i at j * round_up(mtry, 8) + i
   Rec recs[256];      // node j's record of candidate i at j * mtry + i
 };
@@ -662,9 +598,8 @@ struct Shared {
 // the whole code row with five 16-byte loads; the candidate codes are then
 // picked from registers and each is added to the packed bin of its (node,
 // column) histogram (hc columns at a time when they do not all fit the LDS).
-// One wave per (node, column) then scans, the nodes are decided from the
-// per-column records, and a last pass over the chunks sums w y^2 over each
-// split node's left side.
+// One wave per (node, column) then scans, and the nodes are decided from the
+// per-column records.
 template <int BLOCK>
 __device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, uint8_t* lds, Shared& sh) {
   constexpr int NW = BLOCK / kWave;
@@ -687,7 +622,6 @@ __device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, u
     sh.wlen[tid] = d.len;
     sh.wN[tid] = d.N;
     sh.wS[tid] = d.S;
-    sh.wql[tid] = 0;
 #pragma unroll
     for (int j = 0; j < kWideMax; ++j)
       if (j == tid) sh.wcpre[j] = cpre[j];
@@ -773,7 +707,6 @@ __device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, u
         Rec r;
         r.score = am.score;
         r.SL = SL;
-        r.QL = 0;
         r.NL = NL;
         r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
         sh.recs[j * mtry + c0 + i] = r;
@@ -781,33 +714,7 @@ __device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, u
     }
     __syncthreads();
   }
-  if (tid < nb) {
-    const uint32_t k = sh.wk[tid];
-    decide_from_recs(x, k, sh.recs + tid * mtry, mtry);
-    const bool split = x.sc.status[k] == kSplit;
-    sh.wcol[tid] = split ? x.sc.dcol[k] : kLeafCol;
-    sh.wbin[tid] = split ? x.sc.dbin[k] : 0u;
-  }
-  __syncthreads();
-  // left-side sum of w y^2 of every split node of the batch, chunk by chunk
-  for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
-    const int j = node_of(ch);
-    const uint32_t col = sh.wcol[j];
-    if (col == kLeafCol) continue;
-    const uint32_t r = (ch - sh.wcpre[j]) * kWave + (uint32_t)lane;
-    uint64_t val = 0;
-    if (r < sh.wlen[j]) {
-      const uint64_t e = x.buf[sh.wstart[j] + r];
-      if (a.codes_p[(size_t)entry_row(e) * a.Cp + col] <= sh.wbin[j]) {
-        const int64_t y = entry_y(e);
-        val = (uint64_t)((int64_t)entry_w(e) * y * y);
-      }
-    }
-    const uint64_t t = wave_sum(val);
-    if (lane == 0 && t != 0) atomicAdd((unsigned long long*)&sh.wql[j], (unsigned long long)t);
-  }
-  __syncthreads();
-  if (tid < nb && sh.wcol[tid] != kLeafCol) x.sc.dQL[sh.wk[tid]] = sh.wql[tid];
+  if (tid < nb) decide_from_recs(x, sh.wk[tid], sh.recs + tid * mtry, mtry);
   __syncthreads();
 }
 
@@ -985,17 +892,15 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           work_part += en - st;
           sc.curL[k] = st;
           sc.curR[k] = en;
+          sc.qacc[k] = 0;
           const uint32_t NL = sc.dNL[k];
           const int64_t SL = sc.dSL[k];
-          const uint64_t QL = sc.dQL[k];
           X.mstart[2 * r] = st;
           X.mN[2 * r] = NL;
           X.mS[2 * r] = SL;
-          X.mQ[2 * r] = QL;
           X.mend[2 * r + 1] = en;
           X.mN[2 * r + 1] = N - NL;
           X.mS[2 * r + 1] = S - SL;
-          X.mQ[2 * r + 1] = x.mQ[k] - QL;
         } else {
           a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
         }
@@ -1011,16 +916,19 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     }
     // (f) partition the entries of split nodes into their children's segments;
     // the lanes of a wave that send rows of one node to one side share a
-    // single cursor atomic, and take consecutive slots in lane order
+    // single cursor atomic, and take consecutive slots in lane order; the
+    // left side's sum of w y^2 is added up on the way
     for (uint32_t b0 = 0; b0 < n_inbag; b0 += BLOCK) {
       const uint32_t p = b0 + tid;
       const int32_t k = p < n_inbag ? C.slot[p] : -1;
       const bool mv = k >= 0 && sc.status[k] == kSplit;
-      uint64_t e = 0;
+      uint64_t e = 0, wyy = 0;
       uint32_t side = 0;
       if (mv) {
         e = C.buf[p];
         side = a.codes[(size_t)entry_row(e) * a.C + sc.dcol[k]] <= sc.dbin[k] ? 0u : 1u;
+        const int64_t y = entry_y(e);
+        wyy = side ? 0ull : (uint64_t)((int64_t)entry_w(e) * y * y);
       } else if (p < n_inbag) {
         X.slot[p] = -1;
       }
@@ -1043,6 +951,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           const uint32_t kk = (uint32_t)lkey >> 1;
           my_base = (lkey & 1) ? atomicSub(&sc.curR[kk], cnt) - cnt : atomicAdd(&sc.curL[kk], cnt);
         }
+        if ((lkey & 1) == 0) {
+          const uint64_t q = wave_sum(key == lkey ? wyy : 0ull);
+          if (lane == leader) atomicAdd((unsigned long long*)&sc.qacc[(uint32_t)lkey >> 1], (unsigned long long)q);
+        }
       }
       const uint32_t base = (uint32_t)__shfl((int)my_base, my_leader, kWave);
       if (mv) {
@@ -1052,12 +964,15 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       }
     }
     __syncthreads();
-    // (g) the boundary between each pair of children
+    // (g) the boundary between each pair of children, and their sums of w y^2
     for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
       if (sc.status[k] == kSplit) {
         const uint32_t r = sc.rank[k];
+        const uint64_t QL = sc.qacc[k];
         X.mend[2 * r] = sc.curL[k];
         X.mstart[2 * r + 1] = sc.curL[k];
+        X.mQ[2 * r] = QL;
+        X.mQ[2 * r + 1] = x.mQ[k] - QL;
       }
     }
     __syncthreads();
