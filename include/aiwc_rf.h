@@ -134,6 +134,20 @@ int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
                 const int32_t* heldout_fold_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,
                 void* stream);
 
+/* A grid whose forests train on unions of row groups (Sec. III-C: Algorithm 1
+ * omits one kernel per model, Algorithm 2 trains on a random subset of the
+ * kernels and tests on the rest).  group_id: n int8 (device), the group (e.g.
+ * the kernel) of each row in [0, 63], or -1 for rows every forest trains on.
+ * train_mask_host: n_forests uint64 (host); forest k trains on the rows whose
+ * group has its bit set in train_mask_host[k], and holds out the other grouped
+ * rows (see aiwc_rf_heldout_error).  The other arguments, the results and the
+ * errors are those of aiwc_rf_fit (EINVAL also for a group id outside [-1, 63]
+ * and for a mask that selects no row). */
+int aiwc_rf_fit_groups(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                       const double* y_log10, const int8_t* group_id, const uint64_t* train_mask_host,
+                       const aiwc_rf_params* params_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,
+                       void* stream);
+
 /* Wait for an ASYNC fit and return its status (OK, ERANGE, EINVAL). */
 int aiwc_rf_forest_wait(const aiwc_rf_forest* forest);
 
@@ -195,6 +209,27 @@ int aiwc_rf_predict_sum(const aiwc_rf_forest* forest, int32_t forest_index, int3
 int aiwc_rf_oob_error(const aiwc_rf_forest* forest, int32_t forest_begin, int32_t forest_end, const uint8_t* codes,
                       const double* y_log10, int64_t* oob_sum_out, int32_t* oob_count_out, double* mse_host,
                       double* mae_host, int64_t* rows_host, void* stream);
+
+/* Held-out error (Sec. III-C: the error of a model on the kernels it was not
+ * trained on; with aiwc_rf_fit it is the cross-validation error of a fold).  The
+ * held-out rows of a forest are, ascending: for aiwc_rf_fit, the rows of its
+ * held-out fold (none for -1); for aiwc_rf_fit_groups, the grouped rows outside
+ * its mask.  Every held-out row is predicted by all of the forest's trees, as by
+ * aiwc_rf_predict.  Outputs, any of which may be NULL: pred_sum_out (device, one
+ * int64 per held-out row of each forest in turn) gets the exact leaf-value sum
+ * (units 2^-32); mse_host / mae_host / rows_host (forest_end - forest_begin
+ * entries) get the mean squared and mean absolute difference between the
+ * prediction and y over the held-out rows, and their number (0 when a forest
+ * holds out nothing, with mse = mae = 0).  codes and y_log10 must be the arrays
+ * the forest was fitted on.  Synchronous. */
+int aiwc_rf_heldout_error(const aiwc_rf_forest* forest, int32_t forest_begin, int32_t forest_end,
+                          const uint8_t* codes, const double* y_log10, int64_t* pred_sum_out, double* mse_host,
+                          double* mae_host, int64_t* rows_host, void* stream);
+
+/* The held-out rows of forest forest_index: *n_host receives their number and,
+ * unless rows_out_host is NULL, rows_out_host (host, *n_host entries) the row
+ * indices, ascending. */
+int aiwc_rf_heldout_rows(const aiwc_rf_forest* forest, int32_t forest_index, int32_t* rows_out_host, int32_t* n_host);
 
 /* Device selection (Sec. VI: the model is to tell a scheduler on which device a
  * kernel runs fastest).  feature_codes holds m kernels' AIWC feature codes only,

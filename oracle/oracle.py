@@ -227,3 +227,20 @@ def select_device(forest: Forest, feature_codes: np.ndarray, n_devices: int):
     _, yhat = predict(forest, expanded)
     times = yhat.reshape(m, n_devices)
     return np.argmin(times, axis=1).astype(np.int32), times
+
+
+def heldout(forest: Forest, codes: np.ndarray, y: np.ndarray, rows: np.ndarray):
+    """Held-out leaf sums of the given rows (every tree of the forest) and
+    (mse, mae, rows): the mean squared and absolute difference between the
+    forest mean and y, accumulated in row order."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.shape[0] == 0:
+        return np.zeros(0, np.int64), (0.0, 0.0, 0)
+    P, yhat = predict(forest, np.ascontiguousarray(codes[rows]))
+    sq = ab = 0.0
+    for i in range(rows.shape[0]):
+        e = float(yhat[i]) - float(y[rows[i]])
+        sq += e * e
+        ab += abs(e)
+    m = rows.shape[0]
+    return P, (sq / m, ab / m, m)

@@ -270,200 +270,292 @@ void aiwc_rf_binner_free(aiwc_rf_binner* b) {
   delete b;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Training and held-out row lists of a fit: forest k trains on rows
+// train[k] = (offset into rows, count), offset -1 meaning rows 0 .. count-1, and
+// holds out test[k] = (offset into test_rows, count).
+struct RowLists {
+  std::vector<int32_t> rows, test_rows;
+  std::vector<std::pair<int64_t, int32_t>> train, test;
+  template <class Pred>
+  std::pair<int64_t, int32_t> add_train(Pred in, int64_t n) {
+    const int64_t off = (int64_t)rows.size();
+    for (int64_t i = 0; i < n; ++i)
+      if (in(i)) rows.push_back((int32_t)i);
+    const int64_t cnt = (int64_t)rows.size() - off;
+    require(cnt >= 1, "a held-out fold or mask leaves no training rows");
+    return {off, (int32_t)cnt};
+  }
+  template <class Pred>
+  std::pair<int64_t, int32_t> add_test(Pred in, int64_t n) {
+    const int64_t off = (int64_t)test_rows.size();
+    for (int64_t i = 0; i < n; ++i)
+      if (in(i)) test_rows.push_back((int32_t)i);
+    return {off, (int32_t)((int64_t)test_rows.size() - off)};
+  }
+};
+
+void check_fit_args(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                    const double* y_log10, const aiwc_rf_params* params_host, int32_t n_forests, uint32_t flags,
+                    aiwc_rf_forest** forest) {
+  require(codes && binner && y_log10 && params_host && forest, "null pointer argument");
+  require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
+  require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
+          "n_cols must equal the binner's column count");
+  require(n_forests >= 1, "n_forests must be >= 1");
+  require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC | AIWC_RF_FIT_TUNE)) == 0, "unknown flag");
+  int64_t total_trees = 0;
+  for (int32_t f = 0; f < n_forests; ++f) {
+    const aiwc_rf_params& P = params_host[f];
+    require(P.num_trees >= 1 && P.num_trees <= AIWC_RF_MAX_TREES, "num_trees must be in [1, 2^14]");
+    require(P.mtry >= 1 && P.mtry <= n_cols, "mtry must be in [1, n_cols]");
+    require(P.min_node_size >= 1, "min_node_size must be >= 1");
+    require(P.bootstrap == 0 || P.bootstrap == 1, "bootstrap must be 0 or 1");
+    total_trees += P.num_trees;
+  }
+  require(total_trees <= (int64_t)INT32_MAX, "too many trees in one call");
+}
+
+// The fit of n_forests forests whose training (and held-out) rows are given
+// by L; validation of the arguments is done by the caller.
+void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner, const double* y_log10,
+                const aiwc_rf_params* params_host, int32_t n_forests, uint32_t flags, const RowLists& L,
+                aiwc_rf_forest** forest, hipStream_t s) {
+  int64_t total_trees = 0;
+  int32_t mtry_max = 1;
+  for (int32_t f = 0; f < n_forests; ++f) {
+    total_trees += params_host[f].num_trees;
+    mtry_max = std::max(mtry_max, params_host[f].mtry);
+  }
+  const std::vector<int32_t>& train_rows = L.rows;
+  std::unique_ptr<aiwc_rf_forest> F(new aiwc_rf_forest());
+  AIWC_HIP(hipGetDevice(&F->device));
+  F->n_cols = n_cols;
+  F->n_bins = binner->n_bins;
+  F->params.assign(params_host, params_host + n_forests);
+  F->tasks.reserve((size_t)total_trees);
+  int64_t pool = 0, n_cap = 1, inbag_words = 0;
+  for (int32_t f = 0; f < n_forests; ++f) {
+    const aiwc_rf_params& P = params_host[f];
+    const auto& Lf = L.train[f];
+    F->first_task.push_back((int64_t)F->tasks.size());
+    F->n_train.push_back(Lf.second);
+    F->train_off.push_back(Lf.first);
+    F->n_test.push_back(L.test[f].second);
+    F->test_off.push_back(L.test[f].first);
+    const int64_t cap = 2 * (int64_t)Lf.second - 1;
+    n_cap = std::max<int64_t>(n_cap, Lf.second);
+    for (int32_t t = 0; t < P.num_trees; ++t) {
+      TreeTask T;
+      T.forest = f;
+      T.tree = t;
+      T.n_train = Lf.second;
+      T.mtry = P.mtry;
+      T.min_node = P.min_node_size;
+      T.bootstrap = P.bootstrap;
+      T.seed = P.seed;
+      T.train_off = Lf.first;
+      T.node_base = pool;
+      T.capacity = cap;
+      T.inbag_off = P.bootstrap ? inbag_words : -1;
+      if (P.bootstrap) inbag_words += (Lf.second + 63) / 64;
+      pool += cap;
+      F->tasks.push_back(T);
+    }
+  }
+  F->pool_nodes = pool;
+  const int64_t n_tasks = (int64_t)F->tasks.size();
+
+  F->d_tasks.reset((size_t)n_tasks, s);
+  F->nodes.reset((size_t)pool, s);
+  F->node_N.reset((size_t)pool, s);
+  F->n_nodes.reset((size_t)n_tasks, s);
+  F->work.reset((size_t)n_tasks * 4, s);
+  F->node_base.reset((size_t)n_tasks, s);
+  F->status.reset(1, s);
+  AIWC_HIP(hipHostMalloc((void**)&F->status_host, sizeof(uint32_t), hipHostMallocDefault));
+  *F->status_host = 0;
+  AIWC_HIP(hipEventCreateWithFlags(&F->done, hipEventDisableTiming));
+  AIWC_HIP(hipEventCreate(&F->grow_begin));
+  AIWC_HIP(hipEventCreate(&F->grow_end));
+  {
+    std::vector<int64_t> bases((size_t)n_tasks);
+    for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
+    AIWC_HIP(hipMemcpyAsync(F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * n_tasks, hipMemcpyHostToDevice, s));
+    AIWC_HIP(hipMemcpyAsync(F->node_base.p, bases.data(), sizeof(int64_t) * n_tasks, hipMemcpyHostToDevice, s));
+    // the staging copies above read pageable host memory; wait before it goes out of scope
+    AIWC_HIP(hipStreamSynchronize(s));
+  }
+  F->train_rows.reset(train_rows.size(), s);
+  DevBuf<int32_t>& d_train = F->train_rows;
+  if (!train_rows.empty())
+    AIWC_HIP(hipMemcpyAsync(d_train.p, train_rows.data(), sizeof(int32_t) * train_rows.size(), hipMemcpyHostToDevice, s));
+  F->inbag.reset((size_t)inbag_words, s);
+  F->test_rows.reset(L.test_rows.size(), s);
+  if (!L.test_rows.empty())
+    AIWC_HIP(hipMemcpyAsync(F->test_rows.p, L.test_rows.data(), sizeof(int32_t) * L.test_rows.size(),
+                            hipMemcpyHostToDevice, s));
+  DevBuf<int64_t> y_fp((size_t)n, s);
+  DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte row reads
+  DevBuf<uint32_t> queue(1, s);
+
+  GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
+  const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
+  const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
+  if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p,
+                                                d_train.p, queue.p, s);
+
+  if (plain) {
+    // one launch sequence per forest, as separate fits would issue them
+    const int grid_max = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
+    DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
+    launch_init(F->status.p, nullptr, s);
+    AIWC_HIP(hipEventRecord(F->grow_begin, s));
+    for (int32_t f = 0; f < n_forests; ++f) {
+      const int64_t t0 = F->first_task[f];
+      const int32_t nt = params_host[f].num_trees;
+      const int grid = grow_grid_size(cfg, nt, mtry_max, n_cols);
+      launch_init(nullptr, queue.p, s);
+      launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
+      launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
+                  F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, F->inbag.p, queue.p, F->status.p, scratch.p,
+                  n_cap, mtry_max, grid, s);
+    }
+    AIWC_HIP(hipEventRecord(F->grow_end, s));
+  } else {
+    const int grid = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
+    DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
+    if (n_forests > 1) {
+      // fused grid: the whole fit as one captured graph
+      hipStream_t cs;
+      AIWC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipEvent_t ev;
+      AIWC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      AIWC_HIP(hipEventRecord(ev, s));
+      AIWC_HIP(hipStreamWaitEvent(cs, ev, 0));
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      AIWC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        launch_init(F->status.p, queue.p, cs);
+        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, cs);
+        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap,
+                    mtry_max, grid, cs);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        (void)hipEventDestroy(ev);
+        throw;
+      }
+      AIWC_HIP(hipStreamEndCapture(cs, &graph));
+      AIWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      // timing events bracket the whole graph (initialise, prepare, grow)
+      AIWC_HIP(hipEventRecord(F->grow_begin, s));
+      AIWC_HIP(hipGraphLaunch(exec, s));
+      AIWC_HIP(hipEventRecord(F->grow_end, s));
+      AIWC_HIP(hipStreamSynchronize(s));
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cs);
+      (void)hipEventDestroy(ev);
+    } else {
+      launch_init(F->status.p, queue.p, s);
+      launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
+      AIWC_HIP(hipEventRecord(F->grow_begin, s));
+      launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
+                  F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
+                  grid, s);
+      AIWC_HIP(hipEventRecord(F->grow_end, s));
+    }
+  }
+  AIWC_HIP(hipMemcpyAsync(F->status_host, F->status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  AIWC_HIP(hipEventRecord(F->done, s));
+  if (!(flags & AIWC_RF_FIT_ASYNC)) {
+    std::string msg;
+    const int32_t code = resolve_status(F.get(), msg);
+    if (code != AIWC_RF_OK) fail(code, msg);
+  }
+  *forest = F.release();
+}
+
+}  // namespace
+
+extern "C" {
+
 int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner, const double* y_log10,
                 const int8_t* fold_id, const aiwc_rf_params* params_host, const int32_t* heldout_fold_host,
                 int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest, void* stream) {
   return guard([&] {
-    require(codes && binner && y_log10 && params_host && forest, "null pointer argument");
-    require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
-    require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
-            "n_cols must equal the binner's column count");
-    require(n_forests >= 1, "n_forests must be >= 1");
-    require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC | AIWC_RF_FIT_TUNE)) == 0, "unknown flag");
+    check_fit_args(codes, n, n_cols, binner, y_log10, params_host, n_forests, flags, forest);
     hipStream_t s = as_stream(stream);
     bool need_folds = false;
-    int64_t total_trees = 0;
-    int32_t mtry_max = 1;
     for (int32_t f = 0; f < n_forests; ++f) {
-      const aiwc_rf_params& P = params_host[f];
-      require(P.num_trees >= 1 && P.num_trees <= AIWC_RF_MAX_TREES, "num_trees must be in [1, 2^14]");
-      require(P.mtry >= 1 && P.mtry <= n_cols, "mtry must be in [1, n_cols]");
-      require(P.min_node_size >= 1, "min_node_size must be >= 1");
-      require(P.bootstrap == 0 || P.bootstrap == 1, "bootstrap must be 0 or 1");
       const int32_t h = heldout_fold_host ? heldout_fold_host[f] : -1;
       require(h >= -1 && h <= 127, "heldout fold must be in [-1, 127]");
       need_folds |= h >= 0;
-      total_trees += P.num_trees;
-      mtry_max = std::max(mtry_max, P.mtry);
     }
     require(!need_folds || fold_id != nullptr, "fold_id is NULL but a forest holds out a fold");
-    require(total_trees <= (int64_t)INT32_MAX, "too many trees in one call");
-
-    // training-row lists, one per distinct held-out fold
-    std::vector<int32_t> train_rows;
-    std::map<int32_t, std::pair<int64_t, int32_t>> lists;  // fold -> (offset, n_train)
-    lists[-1] = {-1, (int32_t)n};
+    // training and held-out row lists, one pair per distinct held-out fold
+    RowLists L;
+    L.train.assign((size_t)n_forests, {-1, (int32_t)n});
+    L.test.assign((size_t)n_forests, {0, 0});
     if (need_folds) {
       std::vector<int8_t> folds((size_t)n);
       AIWC_HIP(hipMemcpyAsync(folds.data(), fold_id, (size_t)n, hipMemcpyDeviceToHost, s));
       AIWC_HIP(hipStreamSynchronize(s));
-      std::set<int32_t> wanted;
-      for (int32_t f = 0; f < n_forests; ++f)
-        if (heldout_fold_host[f] >= 0) wanted.insert(heldout_fold_host[f]);
-      for (int32_t h : wanted) {
-        const int64_t off = (int64_t)train_rows.size();
-        for (int64_t i = 0; i < n; ++i)
-          if (folds[i] != h) train_rows.push_back((int32_t)i);
-        const int64_t cnt = (int64_t)train_rows.size() - off;
-        require(cnt >= 1, "a held-out fold leaves no training rows");
-        lists[h] = {off, (int32_t)cnt};
-      }
-    }
-
-    std::unique_ptr<aiwc_rf_forest> F(new aiwc_rf_forest());
-    AIWC_HIP(hipGetDevice(&F->device));
-    F->n_cols = n_cols;
-    F->n_bins = binner->n_bins;
-    F->params.assign(params_host, params_host + n_forests);
-    F->tasks.reserve((size_t)total_trees);
-    int64_t pool = 0, n_cap = 1, inbag_words = 0;
-    for (int32_t f = 0; f < n_forests; ++f) {
-      const aiwc_rf_params& P = params_host[f];
-      const auto& L = lists[heldout_fold_host ? heldout_fold_host[f] : -1];
-      F->first_task.push_back((int64_t)F->tasks.size());
-      F->n_train.push_back(L.second);
-      F->train_off.push_back(L.first);
-      const int64_t cap = 2 * (int64_t)L.second - 1;
-      n_cap = std::max<int64_t>(n_cap, L.second);
-      for (int32_t t = 0; t < P.num_trees; ++t) {
-        TreeTask T;
-        T.forest = f;
-        T.tree = t;
-        T.n_train = L.second;
-        T.mtry = P.mtry;
-        T.min_node = P.min_node_size;
-        T.bootstrap = P.bootstrap;
-        T.seed = P.seed;
-        T.train_off = L.first;
-        T.node_base = pool;
-        T.capacity = cap;
-        T.inbag_off = P.bootstrap ? inbag_words : -1;
-        if (P.bootstrap) inbag_words += (L.second + 63) / 64;
-        pool += cap;
-        F->tasks.push_back(T);
-      }
-    }
-    F->pool_nodes = pool;
-    const int64_t n_tasks = (int64_t)F->tasks.size();
-
-    F->d_tasks.reset((size_t)n_tasks, s);
-    F->nodes.reset((size_t)pool, s);
-    F->node_N.reset((size_t)pool, s);
-    F->n_nodes.reset((size_t)n_tasks, s);
-    F->work.reset((size_t)n_tasks * 4, s);
-    F->node_base.reset((size_t)n_tasks, s);
-    F->status.reset(1, s);
-    AIWC_HIP(hipHostMalloc((void**)&F->status_host, sizeof(uint32_t), hipHostMallocDefault));
-    *F->status_host = 0;
-    AIWC_HIP(hipEventCreateWithFlags(&F->done, hipEventDisableTiming));
-    AIWC_HIP(hipEventCreate(&F->grow_begin));
-    AIWC_HIP(hipEventCreate(&F->grow_end));
-    {
-      std::vector<int64_t> bases((size_t)n_tasks);
-      for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
-      AIWC_HIP(hipMemcpyAsync(F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * n_tasks, hipMemcpyHostToDevice, s));
-      AIWC_HIP(hipMemcpyAsync(F->node_base.p, bases.data(), sizeof(int64_t) * n_tasks, hipMemcpyHostToDevice, s));
-      // the staging copies above read pageable host memory; wait before it goes out of scope
-      AIWC_HIP(hipStreamSynchronize(s));
-    }
-    F->train_rows.reset(train_rows.size(), s);
-    DevBuf<int32_t>& d_train = F->train_rows;
-    if (!train_rows.empty())
-      AIWC_HIP(hipMemcpyAsync(d_train.p, train_rows.data(), sizeof(int32_t) * train_rows.size(), hipMemcpyHostToDevice, s));
-    F->inbag.reset((size_t)inbag_words, s);
-    DevBuf<int64_t> y_fp((size_t)n, s);
-    DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte row reads
-    DevBuf<uint32_t> queue(1, s);
-
-    GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
-    const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
-    const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
-    if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p,
-                                                  d_train.p, queue.p, s);
-
-    if (plain) {
-      // one launch sequence per forest, as separate fits would issue them
-      const int grid_max = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
-      DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
-      launch_init(F->status.p, nullptr, s);
-      AIWC_HIP(hipEventRecord(F->grow_begin, s));
+      std::map<int32_t, std::pair<std::pair<int64_t, int32_t>, std::pair<int64_t, int32_t>>> made;
       for (int32_t f = 0; f < n_forests; ++f) {
-        const int64_t t0 = F->first_task[f];
-        const int32_t nt = params_host[f].num_trees;
-        const int grid = grow_grid_size(cfg, nt, mtry_max, n_cols);
-        launch_init(nullptr, queue.p, s);
-        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
-        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, F->inbag.p, queue.p, F->status.p, scratch.p,
-                    n_cap, mtry_max, grid, s);
-      }
-      AIWC_HIP(hipEventRecord(F->grow_end, s));
-    } else {
-      const int grid = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
-      DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
-      if (n_forests > 1) {
-        // fused grid: the whole fit as one captured graph
-        hipStream_t cs;
-        AIWC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipEvent_t ev;
-        AIWC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        AIWC_HIP(hipEventRecord(ev, s));
-        AIWC_HIP(hipStreamWaitEvent(cs, ev, 0));
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        AIWC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        try {
-          launch_init(F->status.p, queue.p, cs);
-          launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, cs);
-          launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                      F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap,
-                      mtry_max, grid, cs);
-        } catch (...) {
-          (void)hipStreamEndCapture(cs, &graph);
-          if (graph) (void)hipGraphDestroy(graph);
-          (void)hipStreamDestroy(cs);
-          (void)hipEventDestroy(ev);
-          throw;
+        const int32_t h = heldout_fold_host[f];
+        if (h < 0) continue;
+        auto it = made.find(h);
+        if (it == made.end()) {
+          const auto tr = L.add_train([&](int64_t i) { return folds[i] != h; }, n);
+          const auto te = L.add_test([&](int64_t i) { return folds[i] == h; }, n);
+          it = made.emplace(h, std::make_pair(tr, te)).first;
         }
-        AIWC_HIP(hipStreamEndCapture(cs, &graph));
-        AIWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        // timing events bracket the whole graph (initialise, prepare, grow)
-        AIWC_HIP(hipEventRecord(F->grow_begin, s));
-        AIWC_HIP(hipGraphLaunch(exec, s));
-        AIWC_HIP(hipEventRecord(F->grow_end, s));
-        AIWC_HIP(hipStreamSynchronize(s));
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        (void)hipStreamDestroy(cs);
-        (void)hipEventDestroy(ev);
-      } else {
-        launch_init(F->status.p, queue.p, s);
-        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
-        AIWC_HIP(hipEventRecord(F->grow_begin, s));
-        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
-                    grid, s);
-        AIWC_HIP(hipEventRecord(F->grow_end, s));
+        L.train[f] = it->second.first;
+        L.test[f] = it->second.second;
       }
     }
-    AIWC_HIP(hipMemcpyAsync(F->status_host, F->status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    AIWC_HIP(hipEventRecord(F->done, s));
-    if (!(flags & AIWC_RF_FIT_ASYNC)) {
-      std::string msg;
-      const int32_t code = resolve_status(F.get(), msg);
-      if (code != AIWC_RF_OK) fail(code, msg);
+    fit_common(codes, n, n_cols, binner, y_log10, params_host, n_forests, flags, L, forest, s);
+  });
+}
+
+int aiwc_rf_fit_groups(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                       const double* y_log10, const int8_t* group_id, const uint64_t* train_mask_host,
+                       const aiwc_rf_params* params_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,
+                       void* stream) {
+  return guard([&] {
+    check_fit_args(codes, n, n_cols, binner, y_log10, params_host, n_forests, flags, forest);
+    require(group_id && train_mask_host, "null pointer argument");
+    hipStream_t s = as_stream(stream);
+    std::vector<int8_t> groups((size_t)n);
+    AIWC_HIP(hipMemcpyAsync(groups.data(), group_id, (size_t)n, hipMemcpyDeviceToHost, s));
+    AIWC_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) require(groups[i] >= -1 && groups[i] <= 63, "group_id must be in [-1, 63]");
+    RowLists L;
+    L.train.resize((size_t)n_forests);
+    L.test.resize((size_t)n_forests);
+    std::map<uint64_t, std::pair<std::pair<int64_t, int32_t>, std::pair<int64_t, int32_t>>> made;
+    for (int32_t f = 0; f < n_forests; ++f) {
+      const uint64_t m = train_mask_host[f];
+      auto it = made.find(m);
+      if (it == made.end()) {
+        const auto in = [&](int64_t i) { return groups[i] < 0 || ((m >> groups[i]) & 1ull) != 0; };
+        const auto tr = L.add_train(in, n);
+        require(tr.second >= 1, "a training mask selects no rows");
+        const auto te = L.add_test([&](int64_t i) { return !in(i); }, n);
+        it = made.emplace(m, std::make_pair(tr, te)).first;
+      }
+      L.train[f] = it->second.first;
+      L.test[f] = it->second.second;
     }
-    *forest = F.release();
+    fit_common(codes, n, n_cols, binner, y_log10, params_host, n_forests, flags, L, forest, s);
   });
 }
 
@@ -656,6 +748,64 @@ int aiwc_rf_oob_error(const aiwc_rf_forest* f, int32_t forest_begin, int32_t for
       if (mae_host) mae_host[k] = res[3 * k + 1];
       if (rows_host) rows_host[k] = (int64_t)res[3 * k + 2];
     }
+  });
+}
+
+int aiwc_rf_heldout_error(const aiwc_rf_forest* f, int32_t forest_begin, int32_t forest_end, const uint8_t* codes,
+                          const double* y_log10, int64_t* pred_sum_out, double* mse_host, double* mae_host,
+                          int64_t* rows_host, void* stream) {
+  return guard([&] {
+    require(f != nullptr, "forest is NULL");
+    require(forest_begin >= 0 && forest_begin < forest_end && forest_end <= (int32_t)f->params.size(),
+            "forest range out of bounds");
+    require(codes && y_log10, "null pointer argument");
+    hipStream_t s = as_stream(stream);
+    require_fitted(f);
+    const int32_t nf = forest_end - forest_begin;
+    std::vector<OobForest> fr((size_t)nf);
+    int64_t rows = 0;
+    int32_t max_n = 0;
+    for (int32_t k = 0; k < nf; ++k) {
+      const int32_t fi = forest_begin + k;
+      fr[k].first_task = f->first_task[fi];
+      fr[k].num_trees = f->params[fi].num_trees;
+      fr[k].n_train = f->n_test[fi];
+      fr[k].train_off = f->test_off[fi];
+      fr[k].row_off = rows;
+      rows += f->n_test[fi];
+      max_n = std::max(max_n, f->n_test[fi]);
+    }
+    std::vector<double> res((size_t)3 * nf, 0.0);
+    if (rows > 0) {
+      DevBuf<OobForest> d_fr((size_t)nf, s);
+      AIWC_HIP(hipMemcpyAsync(d_fr.p, fr.data(), sizeof(OobForest) * nf, hipMemcpyHostToDevice, s));
+      DevBuf<int64_t> sum_tmp(pred_sum_out ? 0 : (size_t)rows, s);
+      DevBuf<int32_t> cnt((size_t)rows, s);
+      const int32_t blocks = std::max(1, (max_n + 255) / 256);
+      DevBuf<double> partial((size_t)3 * nf * blocks, s);
+      DevBuf<double> result((size_t)3 * nf, s);
+      launch_heldout(f->nodes.p, f->node_base.p, f->test_rows.p, d_fr.p, nf, max_n, codes, f->n_cols, y_log10,
+                     pred_sum_out ? pred_sum_out : sum_tmp.p, cnt.p, partial.p, result.p, s);
+      AIWC_HIP(hipMemcpyAsync(res.data(), result.p, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+    }
+    AIWC_HIP(hipStreamSynchronize(s));
+    for (int32_t k = 0; k < nf; ++k) {
+      if (mse_host) mse_host[k] = res[3 * k];
+      if (mae_host) mae_host[k] = res[3 * k + 1];
+      if (rows_host) rows_host[k] = (int64_t)res[3 * k + 2];
+    }
+  });
+}
+
+int aiwc_rf_heldout_rows(const aiwc_rf_forest* f, int32_t forest_index, int32_t* rows_out_host, int32_t* n_host) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    require(n_host != nullptr, "null pointer argument");
+    const int32_t cnt = f->n_test[forest_index];
+    *n_host = cnt;
+    if (rows_out_host && cnt > 0)
+      AIWC_HIP(hipMemcpy(rows_out_host, f->test_rows.p + f->test_off[forest_index], sizeof(int32_t) * cnt,
+                         hipMemcpyDeviceToHost));
   });
 }
 

@@ -134,6 +134,9 @@ struct aiwc_rf_forest {
   aiwc::DevBuf<uint64_t> inbag;            // per tree: bit i set if training row i is in its bootstrap sample
   std::vector<int32_t> n_train;            // per forest
   std::vector<int64_t> train_off;          // per forest, -1 = rows 0 .. n_train-1
+  aiwc::DevBuf<int32_t> test_rows;         // held-out row lists (rows of a held-out fold or outside a mask)
+  std::vector<int32_t> n_test;             // per forest
+  std::vector<int64_t> test_off;           // per forest
 };
 
 namespace aiwc {
@@ -202,6 +205,12 @@ void launch_oob(const uint64_t* nodes, const TreeTask* tasks, const int64_t* nod
                 const int32_t* train_rows, const OobForest* forests, int32_t n_forests, int32_t max_n_train,
                 const uint8_t* codes, int32_t C, const double* y, int64_t* sum, int32_t* count, double* partial,
                 double* result, hipStream_t s);
+// Held-out error: the same per-forest reduction over each forest's held-out
+// rows (OobForest.train_off / n_train name the held-out list in test_rows),
+// every row predicted by all of the forest's trees.
+void launch_heldout(const uint64_t* nodes, const int64_t* node_base, const int32_t* test_rows,
+                    const OobForest* forests, int32_t n_forests, int32_t max_n_test, const uint8_t* codes, int32_t C,
+                    const double* y, int64_t* sum, int32_t* count, double* partial, double* result, hipStream_t s);
 
 // predict.hip
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,

@@ -43,8 +43,31 @@ __global__ __launch_bounds__(kOobBlock) void k_oob_sums(const uint64_t* __restri
   count[F.row_off + i] = cnt;
 }
 
-// Per workgroup: sums of squared error, absolute error and rows with an
-// out-of-bag prediction.
+// Held-out rows: every tree of the forest predicts; count = num.trees, so the
+// prediction formed below is the forest mean of the prediction entry points.
+__global__ __launch_bounds__(kOobBlock) void k_heldout_sums(const uint64_t* __restrict__ nodes,
+                                                            const int64_t* __restrict__ node_base,
+                                                            const int32_t* __restrict__ test_rows,
+                                                            const OobForest* __restrict__ forests,
+                                                            const uint8_t* __restrict__ codes, int32_t C,
+                                                            int64_t* __restrict__ sum, int32_t* __restrict__ count) {
+  const OobForest F = forests[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * kOobBlock + threadIdx.x;
+  if (i >= F.n_train) return;
+  const uint8_t* rp = codes + (int64_t)test_rows[F.train_off + i] * C;
+  int64_t P = 0;
+  for (int32_t t = 0; t < F.num_trees; ++t) {
+    const uint64_t* tn = nodes + node_base[F.first_task + t];
+    uint64_t v = tn[0];
+    while (node_col(v) != kLeafCol) v = tn[node_left(v) + (rp[node_col(v)] > node_bin(v) ? 1u : 0u)];
+    P += node_q(v);
+  }
+  sum[F.row_off + i] = P;
+  count[F.row_off + i] = F.num_trees;
+}
+
+// Per workgroup: sums of squared error, absolute error and rows with a
+// prediction (count > 0).
 __global__ __launch_bounds__(kOobBlock) void k_oob_partial(const int64_t* __restrict__ sum,
                                                            const int32_t* __restrict__ count,
                                                            const int32_t* __restrict__ train_rows,
@@ -119,6 +142,19 @@ void launch_oob(const uint64_t* nodes, const TreeTask* tasks, const int64_t* nod
   k_oob_sums<<<grid, kOobBlock, 0, s>>>(nodes, tasks, node_base, inbag, train_rows, forests, codes, C, sum, count);
   AIWC_HIP(hipGetLastError());
   k_oob_partial<<<grid, kOobBlock, 0, s>>>(sum, count, train_rows, forests, y, partial);
+  AIWC_HIP(hipGetLastError());
+  k_oob_final<<<(n_forests + 255) / 256, 256, 0, s>>>(partial, n_forests, blocks, result);
+  AIWC_HIP(hipGetLastError());
+}
+
+void launch_heldout(const uint64_t* nodes, const int64_t* node_base, const int32_t* test_rows,
+                    const OobForest* forests, int32_t n_forests, int32_t max_n_test, const uint8_t* codes, int32_t C,
+                    const double* y, int64_t* sum, int32_t* count, double* partial, double* result, hipStream_t s) {
+  const int32_t blocks = std::max(1, (max_n_test + kOobBlock - 1) / kOobBlock);
+  const dim3 grid((unsigned)blocks, (unsigned)n_forests);
+  k_heldout_sums<<<grid, kOobBlock, 0, s>>>(nodes, node_base, test_rows, forests, codes, C, sum, count);
+  AIWC_HIP(hipGetLastError());
+  k_oob_partial<<<grid, kOobBlock, 0, s>>>(sum, count, test_rows, forests, y, partial);
   AIWC_HIP(hipGetLastError());
   k_oob_final<<<(n_forests + 255) / 256, 256, 0, s>>>(partial, n_forests, blocks, result);
   AIWC_HIP(hipGetLastError());

@@ -63,6 +63,9 @@ _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_predict_sum", [_P, _i32, _i32, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_select_device", [_P, _i32, _P, _i64, _P, _P, _P])
 _sig("aiwc_rf_oob_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P])
+_sig("aiwc_rf_fit_groups", [_P, _i64, _i32, _P, _P, _P, _P, _P, _i32, _u32, _P, _P])
+_sig("aiwc_rf_heldout_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P])
+_sig("aiwc_rf_heldout_rows", [_P, _i32, _P, _P])
 _sig("aiwc_rf_server_create", [_P, _i32, _i64, _i32, _i32, _P])
 _sig("aiwc_rf_server_submit", [_P, _P, _i64, _P, _P])
 _sig("aiwc_rf_server_poll", [_P, _P, _P, _i32, _P])
@@ -74,7 +77,8 @@ _sig("aiwc_rf_last_error", [], ctypes.c_char_p)
 SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
            "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
-           "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
+           "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
+           "aiwc_rf_heldout_rows", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
 
 
@@ -256,6 +260,69 @@ def aiwc_rf_fit(codes, binner: Binner, y_log10, params, fold_id=None, heldout_fo
                           fp, arr, None if hf is None else _host(hf), len(plist), flags, ctypes.byref(h),
                           _stream(stream)), "aiwc_rf_fit")
     return Forest(h, len(plist))
+
+
+def aiwc_rf_fit_groups(codes, binner: Binner, y_log10, params, group_id, train_mask, flags: int = FIT_FUSED,
+                       stream=None) -> Forest:
+    """A grid whose forest k trains on the rows whose group (int8 device tensor, -1 =
+    always trained on) has its bit set in train_mask[k] (uint64)."""
+    import torch
+
+    n, C = codes.shape
+    plist = [params] if isinstance(params, Params) else list(params)
+    arr = (Params * len(plist))(*plist)
+    masks = np.ascontiguousarray(np.asarray(train_mask, dtype=np.uint64))
+    assert masks.shape[0] == len(plist)
+    h = ctypes.c_void_p()
+    _check(_L.aiwc_rf_fit_groups(_dev(codes, torch.uint8, "codes"), n, C, binner.handle,
+                                 _dev(y_log10, torch.float64, "y"), _dev(group_id, torch.int8, "group_id"), _host(masks),
+                                 arr, len(plist), flags, ctypes.byref(h), _stream(stream)), "aiwc_rf_fit_groups")
+    return Forest(h, len(plist))
+
+
+def aiwc_rf_heldout_rows(forest: Forest, forest_index: int = 0) -> np.ndarray:
+    """Row indices (ascending) that forest forest_index holds out."""
+    cnt = ctypes.c_int32()
+    _check(_L.aiwc_rf_heldout_rows(forest.handle, forest_index, None, ctypes.byref(cnt)), "aiwc_rf_heldout_rows")
+    rows = np.zeros(cnt.value, np.int32)
+    if cnt.value:
+        _check(_L.aiwc_rf_heldout_rows(forest.handle, forest_index, _host(rows), ctypes.byref(cnt)),
+               "aiwc_rf_heldout_rows")
+    return rows
+
+
+@dataclass
+class HeldoutResult:
+    sums: object  # int64 device tensor: leaf sums per held-out row (forests in turn), or None
+    mse: np.ndarray  # per forest
+    mae: np.ndarray
+    rows: np.ndarray
+
+
+def aiwc_rf_heldout_error(forest: Forest, codes, y_log10, forest_begin: int = 0, forest_end: int | None = None,
+                          n_heldout=None, stream=None) -> HeldoutResult:
+    """Held-out predictions and errors of forests [forest_begin, forest_end).
+
+    n_heldout: total held-out rows of those forests (sizes the per-row sums); when
+    omitted the sums are not returned."""
+    import torch
+
+    if forest_end is None:
+        forest_end = forest.n_forests
+    nf = forest_end - forest_begin
+    mse = np.zeros(nf)
+    mae = np.zeros(nf)
+    rows = np.zeros(nf, np.int64)
+    sums = None
+    if n_heldout is not None:
+        sums = torch.empty(max(int(n_heldout), 1), dtype=torch.int64, device=codes.device)
+    _check(_L.aiwc_rf_heldout_error(forest.handle, forest_begin, forest_end, _dev(codes, torch.uint8, "codes"),
+                                    _dev(y_log10, torch.float64, "y"),
+                                    None if sums is None else _dev(sums, torch.int64, "sums"),
+                                    _host(mse), _host(mae), _host(rows), _stream(stream)), "aiwc_rf_heldout_error")
+    if sums is not None:
+        sums = sums[:int(n_heldout)]
+    return HeldoutResult(sums, mse, mae, rows)
 
 
 def aiwc_rf_predict(forest: Forest, codes, forest_index: int = 0, out=None, stream=None):

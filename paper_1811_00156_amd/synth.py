@@ -31,6 +31,7 @@ SEED_D1 = 181100156
 SEED_D3 = 181100157
 SEED_FOLDS = 181100158
 SEED_REQUESTS = 181100159
+SEED_SUBSETS = 181100160
 
 # Held-out fold sizes of the 10-fold cross-validation grid (sum 2220).
 FOLD_SIZES = (199, 245, 210, 233, 222, 215, 229, 204, 240, 223)
@@ -136,6 +137,37 @@ def grid_forests(n_folds: int = 10, mtry_max: int = 34, min_node_sizes=(1, 3, 5,
             for mn in min_node_sizes:
                 out.append((f, m, mn))
     return out
+
+
+def kernel_groups(ds: Dataset, n_sizes: int = 4) -> np.ndarray:
+    """Group id (int8) of every row: the kernel of its (kernel, size) vector, with
+    vector v = kernel * n_sizes + size (37 groups of 4 x 15 = 60 rows in D1)."""
+    return (ds.kernel // n_sizes).astype(np.int8)
+
+
+def leave_one_kernel_out_masks(n_kernels: int = 37) -> np.ndarray:
+    """Training masks of a leave-one-kernel-out study (Sec. III-C, Algorithm 1):
+    forest k trains on every kernel but k."""
+    full = (1 << n_kernels) - 1
+    return np.array([full & ~(1 << k) for k in range(n_kernels)], dtype=np.uint64)
+
+
+def kernel_subset_masks(n_kernels: int = 37, repeats: int = 500, counts=None, seed: int = SEED_SUBSETS):
+    """Training masks of the kernel-count study (Sec. III-C, Algorithm 2): for each
+    count i, `repeats` shuffles of the kernels, training on the first i.  Returns
+    (counts per forest, masks)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = list(range(1, n_kernels + 1)) if counts is None else list(counts)
+    cnt, masks = [], []
+    for i in counts:
+        for _ in range(repeats):
+            order = rng.permutation(n_kernels)
+            m = 0
+            for k in order[:i]:
+                m |= 1 << int(k)
+            cnt.append(i)
+            masks.append(m)
+    return np.array(cnt, dtype=np.int32), np.array(masks, dtype=np.uint64)
 
 
 def request_stream(n_requests: int, qps: float, max_rows: int = 4096, seed: int = SEED_REQUESTS):

@@ -127,3 +127,104 @@ def test_select_device_in_grid(rf, oracle, d1b):
     ob_best, ob_times = oracle.select_device(of, feats, ds.n_devices)
     assert np.array_equal(times.cpu().numpy().view(np.uint64), ob_times.view(np.uint64))
     assert np.array_equal(best.cpu().numpy(), ob_best)
+
+
+# ---------------------------------------------------------------------------- group studies
+def _group_fit(rf, ob, ds, params, masks):
+    g = synth.kernel_groups(ds)
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    return g, codes, y, rf.aiwc_rf_fit_groups(codes, binner, y, params, to_dev(g), masks)
+
+
+@pytest.mark.parametrize("flags", ["fused", "plain"])
+def test_group_study_matches_oracle(rf, oracle, d1b, flags):
+    """Leave-one-kernel-out and kernel-subset forests (Algorithms 1 and 2 of Sec.
+    III-C) against the oracle, tree for tree; held-out sums bit for bit."""
+    log(f"group study {flags}")
+    ds, ob = d1b
+    loo = synth.leave_one_kernel_out_masks()[[0, 17, 36]]
+    cnt, sub = synth.kernel_subset_masks(repeats=2, counts=[1, 5, 36], seed=7)
+    masks = np.concatenate([loo, sub])
+    prm = [(505 if k == 0 else 9, 30, 9) for k in range(len(masks))]
+    params = [rf.make_params(t, m, mn, True, 1) for t, m, mn in prm]
+    g, codes, y = synth.kernel_groups(ds), to_dev(ob.codes), to_dev(ds.y)
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    forest = rf.aiwc_rf_fit_groups(codes, binner, y, params, to_dev(g), masks,
+                                   flags=rf.FIT_FUSED if flags == "fused" else rf.FIT_PLAIN)
+    tests = []
+    for k, m in enumerate(masks):
+        inside = np.array([(int(m) >> int(gi)) & 1 for gi in g], dtype=bool)
+        train, test = np.nonzero(inside)[0], np.nonzero(~inside)[0]
+        tests.append(test)
+        assert np.array_equal(rf.aiwc_rf_heldout_rows(forest, k), test)
+        t, mt, mn = prm[k]
+        of = oracle.fit(ob.codes, ob.n_bins, ds.y, t, mt, mn, seed=1, train_rows=train)
+        check = range(t) if t < 20 else (0, 1, 250, 504)
+        ft = {tt: forest.export(k, tt, tt + 1)[0] for tt in check}
+        for tt in check:
+            from tests._gpu import assert_tree_equal
+
+            assert_tree_equal(ft[tt], of.tree(tt), f"group forest {k} tree {tt}")
+        if t < 20:
+            P, (mse, mae, mrows) = oracle.heldout(of, ob.codes, ds.y, test)
+            tests[-1] = (test, P, mse, mae, mrows)
+    total = sum(len(t[0]) if isinstance(t, tuple) else len(t) for t in tests)
+    res = rf.aiwc_rf_heldout_error(forest, codes, y, n_heldout=total)
+    sums = res.sums.cpu().numpy()
+    off = 0
+    for k, t in enumerate(tests):
+        if isinstance(t, tuple):
+            test, P, mse, mae, mrows = t
+            assert np.array_equal(sums[off:off + len(test)], P), f"forest {k}"
+            assert res.rows[k] == mrows == len(test)
+            assert _close(res.mse[k], mse, mrows) and _close(res.mae[k], mae, mrows)
+            off += len(test)
+        else:
+            off += len(t)
+
+
+def test_fold_grid_heldout_error(rf, oracle, d1b):
+    """Cross-validation error of a fold grid: each forest's held-out fold,
+    predicted by all its trees; a forest that holds out nothing has no rows."""
+    log("fold grid held-out error")
+    ds, ob = d1b
+    folds = synth.cv_folds()
+    combos = [(2, 6, 5), (-1, 12, 1), (9, 20, 3)]
+    params = [rf.make_params(10, m, mn, True, 5) for _, m, mn in combos]
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    forest = rf.aiwc_rf_fit(codes, binner, y, params, fold_id=to_dev(folds), heldout_fold=[c[0] for c in combos])
+    sizes = [int((folds == f).sum()) if f >= 0 else 0 for f, _, _ in combos]
+    res = rf.aiwc_rf_heldout_error(forest, codes, y, n_heldout=sum(sizes))
+    sums = res.sums.cpu().numpy()
+    off = 0
+    for k, (f, m, mn) in enumerate(combos):
+        test = np.nonzero(folds == f)[0] if f >= 0 else np.zeros(0, np.int64)
+        assert np.array_equal(rf.aiwc_rf_heldout_rows(forest, k), test)
+        train = np.nonzero(folds != f)[0] if f >= 0 else None
+        of = oracle.fit(ob.codes, ob.n_bins, ds.y, 10, m, mn, seed=5, train_rows=train)
+        P, (mse, mae, mrows) = oracle.heldout(of, ob.codes, ds.y, test)
+        assert np.array_equal(sums[off:off + len(test)], P)
+        assert res.rows[k] == mrows
+        if mrows:
+            assert _close(res.mse[k], mse, mrows) and _close(res.mae[k], mae, mrows)
+        else:
+            assert res.mse[k] == 0.0 and res.mae[k] == 0.0
+        off += len(test)
+    # the sub-range [1, 3) starts at the second forest's (empty) list
+    r2 = rf.aiwc_rf_heldout_error(forest, codes, y, 1, 3)
+    assert r2.rows.tolist() == [0, sizes[2]] and r2.mse[1] == res.mse[2]
+
+
+def test_group_fit_errors(rf, d1b):
+    ds, ob = d1b
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    codes, y = to_dev(ob.codes), to_dev(ds.y)
+    g = synth.kernel_groups(ds)
+    with pytest.raises(rf.RFError):  # selects no row
+        rf.aiwc_rf_fit_groups(codes, binner, y, [rf.make_params(2, 3, 5)], to_dev(g), [1 << 40])
+    bad = g.copy()
+    bad[5] = 64
+    with pytest.raises(rf.RFError):
+        rf.aiwc_rf_fit_groups(codes, binner, y, [rf.make_params(2, 3, 5)], to_dev(bad), [1])

@@ -60,3 +60,19 @@ def test_argument_checks_without_gpu(lib):
     assert lib.aiwc_rf_binner_from_counts(counts, 3, ctypes.byref(h)) == -1
     lib.aiwc_rf_server_submit.argtypes = [P, P, ctypes.c_int64, P, P]
     assert lib.aiwc_rf_server_submit(None, None, 1, None, None) == -1
+
+
+def test_group_and_heldout_argument_checks_without_gpu(lib):
+    P = ctypes.c_void_p
+    lib.aiwc_rf_fit_groups.restype = ctypes.c_int
+    lib.aiwc_rf_fit_groups.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32,
+                                       ctypes.c_uint32, P, P]
+    h = ctypes.c_void_p()
+    assert lib.aiwc_rf_fit_groups(None, 10, 3, None, None, None, None, None, 1, 0, ctypes.byref(h), None) == -1
+    lib.aiwc_rf_heldout_error.restype = ctypes.c_int
+    lib.aiwc_rf_heldout_error.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
+    assert lib.aiwc_rf_heldout_error(None, 0, 1, None, None, None, None, None, None, None) == -1
+    lib.aiwc_rf_heldout_rows.restype = ctypes.c_int
+    lib.aiwc_rf_heldout_rows.argtypes = [P, ctypes.c_int32, P, P]
+    n = ctypes.c_int32()
+    assert lib.aiwc_rf_heldout_rows(None, 0, None, ctypes.byref(n)) == -1

@@ -127,3 +127,44 @@ def test_select_device_brute_force(oracle, d1_binned):
             row_t.append((float(P) * 2.0 ** -32) / T)
         assert times[i].tolist() == row_t
         assert best[i] == min(range(ds.n_devices), key=lambda d: (row_t[d], d))
+
+
+def test_kernel_groups_and_study_masks():
+    """D1's rows form 37 kernels of 4 sizes x 15 devices; the study masks select
+    exactly the stated number of kernels, every kernel but one, reproducibly."""
+    ds = synth.d1()
+    g = synth.kernel_groups(ds)
+    assert g.dtype == np.int8 and g.min() == 0 and g.max() == 36
+    assert np.all(np.bincount(g) == 60)
+    loo = synth.leave_one_kernel_out_masks()
+    assert [bin(int(m)).count("1") for m in loo] == [36] * 37
+    assert all((int(m) >> k) & 1 == 0 for k, m in enumerate(loo))
+    cnt, masks = synth.kernel_subset_masks(repeats=3, counts=[1, 5, 37])
+    assert cnt.tolist() == [1] * 3 + [5] * 3 + [37] * 3
+    assert [bin(int(m)).count("1") for m in masks] == cnt.tolist()
+    assert all(int(m) < (1 << 37) for m in masks)
+    cnt2, masks2 = synth.kernel_subset_masks(repeats=3, counts=[1, 5, 37])
+    assert np.array_equal(masks, masks2)
+
+
+def test_heldout_matches_brute_force(oracle, d1_binned):
+    """Held-out leaf sums by Python traversal; errors as exact rational means."""
+    ds, b = d1_binned
+    g = synth.kernel_groups(ds)
+    train = np.nonzero(g != 7)[0]
+    test = np.nonzero(g == 7)[0]
+    T = 5
+    f = oracle.fit(b.codes, b.n_bins, ds.y, T, 9, 3, seed=2, train_rows=train)
+    P, (mse, mae, m) = oracle.heldout(f, b.codes, ds.y, test)
+    trees = [f.tree(t) for t in range(T)]
+    ref = [sum(_leaf_q(tr, b.codes[r]) for tr in trees) for r in test]
+    assert P.tolist() == ref and m == test.shape[0] == 60
+    errs = [(float(p) * 2.0 ** -32) / T - float(ds.y[r]) for p, r in zip(ref, test)]
+    ex_mse = sum(Fraction(e) * Fraction(e) for e in errs) / len(errs)
+    ex_mae = sum(abs(Fraction(e)) for e in errs) / len(errs)
+    tol = 2 * len(errs) * 2.0 ** -53
+    assert abs(Fraction(mse) - ex_mse) <= tol * ex_mse
+    assert abs(Fraction(mae) - ex_mae) <= tol * ex_mae
+    # nothing held out: no rows, zero errors
+    P0, (a, b0, m0) = oracle.heldout(f, b.codes, ds.y, np.zeros(0, np.int64))
+    assert P0.shape == (0,) and (a, b0, m0) == (0.0, 0.0, 0)
