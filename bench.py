@@ -15,6 +15,9 @@ devices, 34 features; see paper_1811_00156_amd/synth.py):
   c4  2220 rows, 64 bins, 10 folds x mtry 1..34 x min.node.size {1,3,5,7,9} = 1700 forests x 256 trees,
       fused single launch vs one launch sequence per forest
   c5  serving: the c3 forest answers Poisson request streams of 1..4096 rows
+  studies  the kernel studies of Sec. III-C on 2220 rows, 256 bins, num.trees 505, mtry 30,
+      min.node.size 9: leave-one-kernel-out (37 forests) and training on i = 1..36 random
+      kernels (--repeats forests per i), each forest's held-out kernels predicted on the device
 
 Prints ONE JSON line.  `value` is whole-step throughput in rows x trees per
 second (c5: rows per second).  `roofline` describes the tree-growing kernel:
@@ -42,6 +45,7 @@ WORKLOADS = {
     "c3": dict(data="d3", bins=256, num_trees=500, mtry=16, min_node=5),
     "c4": dict(data="d1", bins=64, num_trees=256),
     "c5": dict(data="d3", bins=256, num_trees=500, mtry=16, min_node=5),
+    "studies": dict(data="d1", bins=256, num_trees=505, mtry=30, min_node=9),
 }
 
 METRIC = "forest fit rows·trees/s (fused grid vs plain); predict rows/s + p99 latency"
@@ -348,6 +352,102 @@ def bench_serve(args):
     }
 
 
+def bench_studies(args):
+    """Algorithm 1 (leave one kernel out) and Algorithm 2 (train on i random kernels,
+    test on the rest) of Sec. III-C as fused group grids, with held-out scoring."""
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    wl = WORKLOADS["studies"]
+    ds = synth.d1()
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(ds.X).to(dev)
+    did = torch.from_numpy(ds.device).to(dev)
+    y = torch.from_numpy(ds.y).to(dev)
+    g = synth.kernel_groups(ds)
+    gd = torch.from_numpy(g).to(dev)
+    codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
+    prm = rf.make_params(wl["num_trees"], wl["mtry"], wl["min_node"], True, 1)
+    per_group = np.bincount(g, minlength=37)
+    loo = synth.leave_one_kernel_out_masks()
+    counts, masks = synth.kernel_subset_masks(repeats=args.repeats, counts=range(1, 37))
+
+    def n_rows(m):
+        return int(sum(per_group[k] for k in range(37) if (int(m) >> k) & 1))
+
+    def run_grid(mask_list):
+        t0 = time.perf_counter()
+        f = rf.aiwc_rf_fit_groups(codes, binner, y, [prm] * len(mask_list), gd, mask_list, flags=tune_flag())
+        t1 = time.perf_counter()
+        h = rf.aiwc_rf_heldout_error(f, codes, y)
+        t2 = time.perf_counter()
+        del f
+        return (t1 - t0) * 1000.0, (t2 - t1) * 1000.0, h
+
+    def run_study(quiet):
+        fit_ms = score_ms = 0.0
+        rows_trees = 0
+        ms1, hs1, h1 = run_grid(loo)
+        fit_ms += ms1
+        score_ms += hs1
+        rows_trees += sum(n_rows(m) for m in loo) * wl["num_trees"]
+        alg1 = float(np.sum(h1.mae * h1.rows) / np.sum(h1.rows))
+        if not quiet:
+            log(f"algorithm 1: 37 forests, fit {ms1:.1f} ms, held-out scoring {hs1:.1f} ms, held-out MAE {alg1:.4f}")
+        maes = []
+        for i in range(1, 37):
+            sel = masks[counts == i]
+            ms, hs, h = run_grid(sel)
+            fit_ms += ms
+            score_ms += hs
+            rows_trees += sum(n_rows(m) for m in sel) * wl["num_trees"]
+            maes.append(float(np.sum(h.mae * h.rows) / np.sum(h.rows)))
+            if not quiet:
+                log(f"algorithm 2: i={i}, {len(sel)} forests, fit {ms:.1f} ms, scoring {hs:.1f} ms, MAE {maes[-1]:.4f}")
+        return fit_ms, score_ms, rows_trees, alg1, maes
+
+    # the warmup runs the whole study once, so that every problem shape's launch
+    # shape is tuned before the timed pass
+    for i in range(min(args.warmup, 1)):
+        log("studies warmup: the whole study once")
+        run_study(True)
+    torch.cuda.synchronize()
+    fit_ms, score_ms, rows_trees, alg1_mae, mae_by_count = run_study(False)
+    total_ms = fit_ms + score_ms
+    n_forests = 37 + int(len(masks))
+    res = {
+        "metric": "kernel-study forest fit + held-out scoring rows·trees/s", "value": rows_trees / (total_ms / 1000.0),
+        "unit": "rows·trees/s", "n_gpus": 1, "steps": 1, "warmup": min(args.warmup, 1), "ms_per_step": total_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": f"studies: 2220 rows, 256 bins, num.trees 505, mtry 30, min.node.size 9; "
+                               f"37 leave-one-kernel-out forests + {len(masks)} kernel-subset forests "
+                               f"(i = 1..36, {args.repeats} each)", "forests": n_forests},
+        "fit_ms": fit_ms, "heldout_scoring_ms": score_ms, "alg1_heldout_mae": alg1_mae,
+        "alg2_mae_by_kernel_count": mae_by_count,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        ob = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
+        # every 100th study forest (all kernel counts), all 505 trees each
+        sample = list(loo[:1]) + list(masks[::100])
+        t0 = time.perf_counter()
+        rt = 0
+        for m in sample:
+            inside = np.array([(int(m) >> int(k)) & 1 for k in g], dtype=bool)
+            train = np.nonzero(inside)[0]
+            O.fit(ob.codes, ob.n_bins, ds.y, wl["num_trees"], wl["mtry"], wl["min_node"], seed=1, train_rows=train,
+                  n_threads=cores)
+            rt += train.shape[0] * wl["num_trees"]
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{len(sample)} study forests (one leave-one-kernel-out, every 100th "
+                                         f"kernel subset), 505 trees each, {el:.1f} s"}
+    return res
+
+
 def bench_copy(args):
     """A plain device-to-device copy of known size: the reference that scales
     rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -378,6 +478,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy"])
     ap.add_argument("--requests", type=int, default=4000)
+    ap.add_argument("--repeats", type=int, default=100, help="studies: kernel subsets per kernel count (paper: 500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-shape", action="store_true",
                     help="no autotuning: grow with AIWC_RF_GROW_BLOCK / AIWC_RF_HUGE_MIN or the defaults")
@@ -399,6 +500,8 @@ def main():
         res = bench_grid(args)
     elif args.workload == "c5":
         res = bench_serve(args)
+    elif args.workload == "studies":
+        res = bench_studies(args)
     else:
         res = bench_forest(args, args.workload)
     print(json.dumps(res))
