@@ -231,6 +231,63 @@ int aiwc_rf_heldout_error(const aiwc_rf_forest* forest, int32_t forest_begin, in
  * indices, ascending. */
 int aiwc_rf_heldout_rows(const aiwc_rf_forest* forest, int32_t forest_index, int32_t* rows_out_host, int32_t* n_host);
 
+/* ------------------------------------------------------------------------------
+ * Parameter search by simulated annealing (Sec. III-B: num.trees, mtry and
+ * min.node.size are chosen by an annealing search that minimises the
+ * out-of-bag error, from a starting location).
+ *
+ * The state is the parameter triple (num.trees, mtry, min.node.size), each in
+ * [lower, upper].  The objective of a triple is the out-of-bag MSE of the forest
+ * grown with it on all n rows (bootstrap, seed cfg->seed), summed on the host in
+ * row order from the exact out-of-bag sums and counts, so that the whole search
+ * is reproducible bit for bit.  The start is evaluated first.  At level l
+ * (temperature T_l = t0 * cooling^l) `proposals` triples are drawn around the
+ * state the level starts from: proposal j of level l takes block (0, 2, l, j)
+ * of the Philox4x64-10 stream keyed (seed, 0); word c (c = 0, 1, 2) moves
+ * coordinate c by floor(word * (2h_c + 1) / 2^64) - h_c, with half-width h_c =
+ * max(1, floor(step_frac * (upper_c - lower_c))), clamped to the bounds; word
+ * 3 gives u = (word >> 11) * 2^-53.  All proposals of a level are fitted
+ * together as one grid and scored; then, in proposal order, a proposal whose
+ * objective is not above the current one's, or whose u < exp(-(f' - f) / T_l),
+ * becomes the current state.  The best triple over every evaluation (the first
+ * on ties) is returned.
+ */
+typedef struct {
+  int32_t lower[3];   /* bounds of num.trees, mtry, min.node.size (inclusive) */
+  int32_t upper[3];
+  int32_t start[3];   /* starting location */
+  int32_t levels;     /* temperature levels */
+  int32_t proposals;  /* proposals per level, fitted together */
+  double t0;          /* initial temperature, in units of the objective */
+  double cooling;     /* T_{l+1} = cooling * T_l */
+  double step_frac;   /* proposal half-width as a fraction of each range */
+  uint64_t seed;      /* forest seed and annealing stream key */
+} aiwc_rf_sa_config;
+
+/* One evaluation of the search: level (-1 for the start), proposal index, the
+ * triple, its objective and out-of-bag row count, whether it was accepted, and
+ * the current triple after the decision. */
+typedef struct {
+  int32_t level;
+  int32_t index;
+  int32_t params[3];
+  int32_t accepted;
+  int32_t current[3];
+  int64_t oob_rows;
+  double objective;
+} aiwc_rf_sa_step;
+
+/* Run the search on n rows of codes (device, n x n_cols, the binner's codes) and
+ * y_log10 (device).  best_params_host (3 ints) and best_objective_host receive
+ * the best triple and its objective; trace_host (1 + levels * proposals
+ * entries, or NULL) every evaluation in order.  Errors: EINVAL for bounds with
+ * lower > upper, a start outside them, mtry bounds outside [1, n_cols], levels
+ * or proposals < 1, non-finite or negative t0, cooling or step_frac; the errors
+ * of aiwc_rf_fit.  Synchronous. */
+int aiwc_rf_tune_sa(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                    const double* y_log10, const aiwc_rf_sa_config* cfg, int32_t* best_params_host,
+                    double* best_objective_host, aiwc_rf_sa_step* trace_host, void* stream);
+
 /* Device selection (Sec. VI: the model is to tell a scheduler on which device a
  * kernel runs fastest).  feature_codes holds m kernels' AIWC feature codes only,
  * m x (n_cols - 1) uint8 row-major (device); every device id 0 .. D-1 (D = the

@@ -10,6 +10,7 @@ NumPy arrays.  Every function follows the readings documented in
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -244,3 +245,61 @@ def heldout(forest: Forest, codes: np.ndarray, y: np.ndarray, rows: np.ndarray):
         ab += abs(e)
     m = rows.shape[0]
     return P, (sq / m, ab / m, m)
+
+
+def anneal(objective, lower, upper, start, levels: int, proposals: int, t0: float, cooling: float,
+           step_frac: float, seed: int):
+    """Simulated annealing over integer triples (num.trees, mtry, min.node.size).
+
+    objective(list of triples) -> list of (value, oob_rows).  The start is scored
+    first.  Level l (temperature t0 * cooling^l) draws `proposals` triples around
+    the state it starts from, proposal j from Philox block (0, 2, l, j) with key
+    (seed, 0): word c moves coordinate c by floor(word * (2h_c + 1) / 2^64) - h_c
+    with h_c = max(1, floor(step_frac * (upper_c - lower_c))), clamped to the
+    bounds; word 3 gives u = (word >> 11) * 2^-53.  All proposals are scored, then
+    taken in order: accepted if not worse than the current value, or if
+    u < exp(-(worse by) / T).  Returns (best triple, best value, trace), the best
+    being the first evaluation with the lowest value."""
+    half = [max(1, math.floor(step_frac * (upper[c] - lower[c]))) for c in range(3)]
+    cur = tuple(start)
+    f_cur, rows = objective([cur])[0]
+    trace = [dict(level=-1, index=0, params=cur, accepted=True, current=cur, oob_rows=rows, objective=f_cur)]
+    best, f_best = cur, f_cur
+    T = t0
+    for level in range(levels):
+        base = cur
+        props, us = [], []
+        for j in range(proposals):
+            w = [int(v) for v in philox([0, 2, level, j], [seed, 0])]
+            p = []
+            for c in range(3):
+                step = (w[c] * (2 * half[c] + 1)) >> 64
+                p.append(min(upper[c], max(lower[c], base[c] + step - half[c])))
+            props.append(tuple(p))
+            us.append((w[3] >> 11) * 2.0 ** -53)
+        scores = objective(props)
+        for j, (p, (f, r)) in enumerate(zip(props, scores)):
+            d = f - f_cur
+            if T > 0.0:
+                accept = d <= 0.0 or us[j] < math.exp(-d / T)
+            else:
+                accept = d <= 0.0
+            if accept:
+                cur, f_cur = p, f
+            if f < f_best:
+                best, f_best = p, f
+            trace.append(dict(level=level, index=j, params=p, accepted=accept, current=cur, oob_rows=r, objective=f))
+        T *= cooling
+    return best, f_best, trace
+
+
+def oob_objective(codes: np.ndarray, n_bins: np.ndarray, y: np.ndarray, seed: int):
+    """The annealing objective: out-of-bag MSE of the forest grown with a triple on all rows."""
+    def score(triples):
+        out = []
+        for nt, mt, mn in triples:
+            f = fit(codes, n_bins, y, nt, mt, mn, seed=seed)
+            _, _, (mse, _, rows) = oob(f, codes, y, mt, mn, seed=seed)
+            out.append((mse, rows))
+        return out
+    return score

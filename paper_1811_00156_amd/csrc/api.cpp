@@ -797,6 +797,19 @@ int aiwc_rf_heldout_error(const aiwc_rf_forest* f, int32_t forest_begin, int32_t
   });
 }
 
+int aiwc_rf_tune_sa(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
+                    const double* y_log10, const aiwc_rf_sa_config* cfg, int32_t* best_params_host,
+                    double* best_objective_host, aiwc_rf_sa_step* trace_host, void* stream) {
+  return guard([&] {
+    require(codes && binner && y_log10 && cfg && best_params_host && best_objective_host, "null pointer argument");
+    require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
+    require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
+            "n_cols must equal the binner's column count");
+    anneal(codes, n, n_cols, binner, y_log10, *cfg, best_params_host, best_objective_host, trace_host,
+           as_stream(stream));
+  });
+}
+
 int aiwc_rf_heldout_rows(const aiwc_rf_forest* f, int32_t forest_index, int32_t* rows_out_host, int32_t* n_host) {
   return guard([&] {
     check_forest(f, forest_index);

@@ -212,6 +212,11 @@ void launch_heldout(const uint64_t* nodes, const int64_t* node_base, const int32
                     const OobForest* forests, int32_t n_forests, int32_t max_n_test, const uint8_t* codes, int32_t C,
                     const double* y, int64_t* sum, int32_t* count, double* partial, double* result, hipStream_t s);
 
+// tune.cpp: the annealing search of aiwc_rf_tune_sa (arguments checked there).
+void anneal(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner, const double* y_dev,
+            const aiwc_rf_sa_config& cfg, int32_t* best_params, double* best_objective, aiwc_rf_sa_step* trace,
+            hipStream_t s);
+
 // predict.hip
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                     const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,

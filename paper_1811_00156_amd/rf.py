@@ -66,6 +66,7 @@ _sig("aiwc_rf_oob_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_fit_groups", [_P, _i64, _i32, _P, _P, _P, _P, _P, _i32, _u32, _P, _P])
 _sig("aiwc_rf_heldout_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_heldout_rows", [_P, _i32, _P, _P])
+_sig("aiwc_rf_tune_sa", [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_server_create", [_P, _i32, _i64, _i32, _i32, _P])
 _sig("aiwc_rf_server_submit", [_P, _P, _i64, _P, _P])
 _sig("aiwc_rf_server_poll", [_P, _P, _P, _i32, _P])
@@ -78,7 +79,7 @@ SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_h
            "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
            "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
-           "aiwc_rf_heldout_rows", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
+           "aiwc_rf_heldout_rows", "aiwc_rf_tune_sa", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
 
 
@@ -323,6 +324,44 @@ def aiwc_rf_heldout_error(forest: Forest, codes, y_log10, forest_begin: int = 0,
     if sums is not None:
         sums = sums[:int(n_heldout)]
     return HeldoutResult(sums, mse, mae, rows)
+
+
+class SAConfig(ctypes.Structure):
+    _fields_ = [("lower", ctypes.c_int32 * 3), ("upper", ctypes.c_int32 * 3), ("start", ctypes.c_int32 * 3),
+                ("levels", ctypes.c_int32), ("proposals", ctypes.c_int32), ("t0", ctypes.c_double),
+                ("cooling", ctypes.c_double), ("step_frac", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class SAStep(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("index", ctypes.c_int32), ("params", ctypes.c_int32 * 3),
+                ("accepted", ctypes.c_int32), ("current", ctypes.c_int32 * 3), ("oob_rows", ctypes.c_int64),
+                ("objective", ctypes.c_double)]
+
+
+def sa_config(lower, upper, start, levels: int, proposals: int, t0: float, cooling: float, step_frac: float,
+              seed: int = 1) -> SAConfig:
+    c = SAConfig()
+    c.lower[:] = list(lower)
+    c.upper[:] = list(upper)
+    c.start[:] = list(start)
+    c.levels, c.proposals, c.t0, c.cooling, c.step_frac, c.seed = levels, proposals, t0, cooling, step_frac, seed
+    return c
+
+
+def aiwc_rf_tune_sa(codes, binner: Binner, y_log10, cfg: SAConfig, stream=None):
+    """Annealing search of (num.trees, mtry, min.node.size) by out-of-bag MSE:
+    (best triple, best objective, list of trace dicts in evaluation order)."""
+    import torch
+
+    n, C = codes.shape
+    best = (ctypes.c_int32 * 3)()
+    best_f = ctypes.c_double()
+    trace = (SAStep * (1 + cfg.levels * cfg.proposals))()
+    _check(_L.aiwc_rf_tune_sa(_dev(codes, torch.uint8, "codes"), n, C, binner.handle, _dev(y_log10, torch.float64, "y"),
+                              ctypes.byref(cfg), best, ctypes.byref(best_f), trace, _stream(stream)), "aiwc_rf_tune_sa")
+    steps = [{"level": t.level, "index": t.index, "params": tuple(t.params), "accepted": bool(t.accepted),
+              "current": tuple(t.current), "oob_rows": t.oob_rows, "objective": t.objective} for t in trace]
+    return tuple(best), best_f.value, steps
 
 
 def aiwc_rf_predict(forest: Forest, codes, forest_index: int = 0, out=None, stream=None):

@@ -228,3 +228,34 @@ def test_group_fit_errors(rf, d1b):
     bad[5] = 64
     with pytest.raises(rf.RFError):
         rf.aiwc_rf_fit_groups(codes, binner, y, [rf.make_params(2, 3, 5)], to_dev(bad), [1])
+
+
+# ---------------------------------------------------------------------------- annealing search
+def test_anneal_matches_oracle(rf, oracle):
+    """The device search takes the same path as the oracle's: every proposal,
+    objective (binary64 bit pattern), decision and the best triple."""
+    log("annealing search")
+    ds = synth.small(n_vec=60, n_devices=6, p_ln=6, p_u=4, seed=31)  # 360 rows, 11 code columns
+    ob = oracle.bin(ds.X, ds.device, ds.n_devices, 64)
+    lower, upper, start = (2, 1, 1), (16, 11, 30), (8, 5, 10)
+    args = dict(levels=4, proposals=6, t0=0.05, cooling=0.5, step_frac=0.3, seed=17)
+    cfg = rf.sa_config(lower, upper, start, **args)
+    best, fb, trace = rf.aiwc_rf_tune_sa(to_dev(ob.codes), rf.aiwc_rf_binner_from_counts(ob.n_bins), to_dev(ds.y), cfg)
+    obest, ofb, otrace = oracle.anneal(oracle.oob_objective(ob.codes, ob.n_bins, ds.y, 17), lower, upper, start,
+                                       **args)
+    assert len(trace) == len(otrace) == 25
+    for g, o in zip(trace, otrace):
+        assert (g["level"], g["index"], g["params"], g["accepted"], g["current"], g["oob_rows"]) == \
+            (o["level"], o["index"], o["params"], o["accepted"], o["current"], o["oob_rows"]), (g, o)
+        assert np.float64(g["objective"]).view(np.uint64) == np.float64(o["objective"]).view(np.uint64)
+    assert best == obest and fb == ofb
+    assert any(not t["accepted"] for t in trace) and any(t["accepted"] for t in trace[1:])
+
+
+def test_anneal_errors(rf, d1b):
+    ds, ob = d1b
+    codes, y, binner = to_dev(ob.codes), to_dev(ds.y), rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    for lo, up, st in (((5, 1, 1), (4, 3, 3), (5, 1, 1)), ((1, 1, 1), (9, 40, 3), (2, 2, 2)),
+                       ((1, 1, 1), (9, 3, 3), (10, 2, 2))):
+        with pytest.raises(rf.RFError):
+            rf.aiwc_rf_tune_sa(codes, binner, y, rf.sa_config(lo, up, st, 1, 1, 0.1, 0.5, 0.1))

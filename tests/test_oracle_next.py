@@ -168,3 +168,74 @@ def test_heldout_matches_brute_force(oracle, d1_binned):
     # nothing held out: no rows, zero errors
     P0, (a, b0, m0) = oracle.heldout(f, b.codes, ds.y, np.zeros(0, np.int64))
     assert P0.shape == (0,) and (a, b0, m0) == (0.0, 0.0, 0)
+
+
+# ---------------------------------------------------------------------------- annealing search
+def _numpy_proposals(seed, level, proposals, base, lower, upper, step_frac):
+    """Proposals and uniforms of one level from NumPy's own Philox4x64-10."""
+    from _ref import numpy_block
+
+    half = [max(1, int(step_frac * (upper[c] - lower[c]))) for c in range(3)]
+    out = []
+    for j in range(proposals):
+        w = [int(v) for v in numpy_block([0, 2, level, j], [seed, 0])[0]]
+        p = tuple(min(upper[c], max(lower[c], base[c] + ((w[c] * (2 * half[c] + 1)) >> 64) - half[c]))
+                  for c in range(3))
+        out.append((p, (w[3] >> 11) / 2.0 ** 53))
+    return out
+
+
+def test_anneal_proposals_follow_the_philox_stream(oracle):
+    """A flat objective accepts every proposal, so each level starts from the
+    previous level's last proposal; the proposals equal NumPy's Philox draws."""
+    lower, upper, start = (1, 1, 1), (1000, 35, 50), (500, 17, 25)
+    best, fb, trace = oracle.anneal(lambda ts: [(1.0, 7)] * len(ts), lower, upper, start, 3, 4, 1.0, 0.5, 0.1, 99)
+    assert all(t["accepted"] for t in trace) and best == start and fb == 1.0
+    base = start
+    for level in range(3):
+        expect = _numpy_proposals(99, level, 4, base, lower, upper, 0.1)
+        got = [t["params"] for t in trace if t["level"] == level]
+        assert got == [p for p, _ in expect]
+        base = got[-1]
+
+
+def test_anneal_greedy_reaches_the_optimum(oracle):
+    """At zero temperature only non-worsening proposals are taken; with unit steps
+    on a separable convex objective the search ends at its minimum, and the best
+    is the lowest value met (first on ties)."""
+    target = (40, 5, 7)
+    obj = lambda ts: [(float(sum((a - b) ** 2 for a, b in zip(t, target))), 1) for t in ts]
+    best, fb, trace = oracle.anneal(obj, (1, 1, 1), (64, 12, 16), (3, 11, 15), 60, 8, 0.0, 0.9, 0.0, 3)
+    assert best == target and fb == 0.0
+    f_cur = trace[0]["objective"]
+    for t in trace[1:]:
+        assert t["accepted"] == (t["objective"] <= f_cur)
+        if t["accepted"]:
+            f_cur = t["objective"]
+    vals = [t["objective"] for t in trace]
+    assert fb == min(vals) and trace[vals.index(min(vals))]["params"] == best
+
+
+def test_anneal_hot_accepts_everything_and_respects_bounds(oracle):
+    obj = lambda ts: [(float(t[0] * 7 % 13 + t[1] + t[2]), 1) for t in ts]
+    lower, upper = (2, 1, 3), (9, 4, 8)
+    best, fb, trace = oracle.anneal(obj, lower, upper, (5, 2, 3), 10, 6, 1e300, 1.0, 0.5, 11)
+    assert all(t["accepted"] for t in trace)
+    for t in trace:
+        assert all(lower[c] <= t["params"][c] <= upper[c] for c in range(3))
+
+
+def test_anneal_accepts_worse_by_metropolis(oracle):
+    """A worse proposal is taken iff u < exp(-(f' - f) / T), u from the stream."""
+    obj = lambda ts: [(float(t[0]), 1) for t in ts]  # lower num.trees is better
+    lower, upper, start = (1, 1, 1), (100, 1, 1), (50, 1, 1)
+    best, fb, trace = oracle.anneal(obj, lower, upper, start, 1, 16, 5.0, 1.0, 0.2, 5)
+    draws = _numpy_proposals(5, 0, 16, start, lower, upper, 0.2)
+    f_cur = 50.0
+    import math
+
+    for (p, u), t in zip(draws, trace[1:]):
+        d = p[0] - f_cur
+        assert t["accepted"] == (d <= 0 or u < math.exp(-d / 5.0))
+        if t["accepted"]:
+            f_cur = float(p[0])
