@@ -18,6 +18,8 @@ devices, 34 features; see paper_1811_00156_amd/synth.py):
   studies  the kernel studies of Sec. III-C on 2220 rows, 256 bins, num.trees 505, mtry 30,
       min.node.size 9: leave-one-kernel-out (37 forests) and training on i = 1..36 random
       kernels (--repeats forests per i), each forest's held-out kernels predicted on the device
+  tune  the annealing search of Sec. III-B on 2220 rows, 256 bins: num.trees 10..1000, mtry 1..35,
+      min.node.size 1..50 from (500, 17, 5), 10 levels x 32 proposals fitted together per level
 
 Prints ONE JSON line.  `value` is whole-step throughput in rows x trees per
 second (c5: rows per second).  `roofline` describes the tree-growing kernel:
@@ -46,6 +48,8 @@ WORKLOADS = {
     "c4": dict(data="d1", bins=64, num_trees=256),
     "c5": dict(data="d3", bins=256, num_trees=500, mtry=16, min_node=5),
     "studies": dict(data="d1", bins=256, num_trees=505, mtry=30, min_node=9),
+    "tune": dict(data="d1", bins=256, lower=(10, 1, 1), upper=(1000, 35, 50), start=(500, 17, 5), levels=10,
+                 proposals=32, t0=0.02, cooling=0.7, step_frac=0.15),
 }
 
 METRIC = "forest fit rows·trees/s (fused grid vs plain); predict rows/s + p99 latency"
@@ -431,8 +435,9 @@ def bench_studies(args):
 
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         ob = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
-        # every 100th study forest (all kernel counts), all 505 trees each
-        sample = list(loo[:1]) + list(masks[::100])
+        # one leave-one-kernel-out forest and every 25th kernel subset (all counts), 505 trees each
+        step = max(1, len(masks) // 144)
+        sample = list(loo[:1]) + list(masks[::step])
         t0 = time.perf_counter()
         rt = 0
         for m in sample:
@@ -443,8 +448,61 @@ def bench_studies(args):
             rt += train.shape[0] * wl["num_trees"]
         el = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{len(sample)} study forests (one leave-one-kernel-out, every 100th "
+                               "sample": f"{len(sample)} study forests (one leave-one-kernel-out, every {step}th "
                                          f"kernel subset), 505 trees each, {el:.1f} s"}
+    return res
+
+
+def bench_tune(args):
+    """The annealing parameter search: every level's proposals in one fused fit,
+    scored by out-of-bag error on the device."""
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    wl = WORKLOADS["tune"]
+    ds = synth.d1()
+    dev = torch.device("cuda:0")
+    codes, binner = rf.aiwc_rf_bin(torch.from_numpy(ds.X).to(dev), torch.from_numpy(ds.device).to(dev),
+                                   ds.n_devices, wl["bins"])
+    y = torch.from_numpy(ds.y).to(dev)
+    cfg = rf.sa_config(wl["lower"], wl["upper"], wl["start"], wl["levels"], wl["proposals"], wl["t0"], wl["cooling"],
+                       wl["step_frac"], seed=1)
+    for i in range(min(args.warmup, 1)):
+        log("tune warmup: the whole search once")
+        rf.aiwc_rf_tune_sa(codes, binner, y, cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, fb, trace = rf.aiwc_rf_tune_sa(codes, binner, y, cfg)
+    ms = (time.perf_counter() - t0) * 1000.0
+    rows_trees = sum(ds.n * t["params"][0] for t in trace)
+    log(f"tune: {len(trace)} forests in {ms:.1f} ms; best {best} OOB MSE {fb:.5f} "
+        f"(start {trace[0]['params']} OOB MSE {trace[0]['objective']:.5f}); "
+        f"accepted {sum(t['accepted'] for t in trace[1:])} of {len(trace) - 1}")
+    res = {
+        "metric": "annealing search forest fit + out-of-bag scoring rows·trees/s", "value": rows_trees / (ms / 1000.0),
+        "unit": "rows·trees/s", "n_gpus": 1, "steps": 1, "warmup": min(args.warmup, 1), "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": "tune: 2220 rows, 256 bins; num.trees 10..1000, mtry 1..35, min.node.size 1..50 "
+                               "from (500, 17, 5); 10 levels x 32 proposals", "forests": len(trace)},
+        "best_params": list(best), "best_oob_mse": fb, "start_oob_mse": trace[0]["objective"],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        ob = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
+        # the oracle's objective on every 10th triple the search evaluated
+        sample = [t["params"] for t in trace[::10]]
+        t0 = time.perf_counter()
+        rt = 0
+        for nt, mt, mn in sample:
+            f = O.fit(ob.codes, ob.n_bins, ds.y, nt, mt, mn, seed=1, n_threads=cores)
+            O.oob(f, ob.codes, ds.y, mt, mn, seed=1)
+            rt += ds.n * nt
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+                               "sample": f"fit + out-of-bag error of {len(sample)} of the search's triples, {el:.1f} s"}
     return res
 
 
@@ -502,6 +560,8 @@ def main():
         res = bench_serve(args)
     elif args.workload == "studies":
         res = bench_studies(args)
+    elif args.workload == "tune":
+        res = bench_tune(args)
     else:
         res = bench_forest(args, args.workload)
     print(json.dumps(res))
