@@ -314,55 +314,58 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   const int64_t y = entry_y(e);
   const int64_t wy = (int64_t)w * y;
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
-  int64_t* s_wy = reinterpret_cast<int64_t*>(area);        // [64]
-  uint32_t* s_w = reinterpret_cast<uint32_t*>(area + 512);  // [64]
-  s_wy[lane] = wy;
-  s_w[lane] = w;
+  uint64_t* s_pv = reinterpret_cast<uint64_t*>(area);  // [64] packed (w, w y)
+  uint8_t* s_codes = area + 512;                       // [64 columns][64 lanes]
+  s_pv[lane] = pack_ns(w, wy);
   const uint8_t* rowp = a.codes + (size_t)row * a.C;
   const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
 
+  // each lane keeps its own best split (score, candidate index, bin) over the
+  // candidates in order; one segment arg-max at the end picks the node's
   double best = -1.0;
-  uint32_t best_cb = 0xFFFFFFFFu;
-  uint8_t* s_codes = area + 1024;  // [64 columns][64 lanes]
+  uint32_t best_ib = 0xFFFFFFFFu;  // candidate index << 8 | bin
+  const uint64_t* seg_pv = s_pv + sbase;
   for (int i0 = 0; i0 < mtry; i0 += kWave) {
     const int nc = min(kWave, mtry - i0);
     // gather the row's codes in every candidate column of this chunk at once
 #pragma unroll 8
     for (int i = 0; i < nc; ++i) s_codes[i * kWave + lane] = valid ? rowp[node_ok ? cand[i0 + i] : 0] : 0;
     wave_lds_sync();
-    for (int i = i0; i < i0 + nc; ++i) {
-      const uint32_t c = node_ok ? cand[i] : 0u;
-      const uint8_t* col_codes = s_codes + (i - i0) * kWave;
+    for (int i = 0; i < nc; ++i) {
+      const uint8_t* col_codes = s_codes + i * kWave;
       const uint32_t code = col_codes[lane];
-      uint32_t NL = 0;
-      int64_t SL = 0;
-#pragma unroll 4
-      for (int b = 0; b < W; ++b) {
-        const bool in = col_codes[sbase + b] <= code;
-        NL += in ? s_w[sbase + b] : 0u;
-        SL += in ? s_wy[sbase + b] : 0;
-      }
-      double sc = -1.0;
-      if (valid && NL < N) sc = split_score(SL, NL, S - SL, N - NL);
-      uint32_t key = code;
+      const uint32_t* seg_codes = reinterpret_cast<const uint32_t*>(col_codes + sbase);
+      uint64_t acc = 0;  // packed left sums of the split at this lane's code
+#pragma unroll 2
+      for (int b4 = 0; b4 < W / 4; ++b4) {
+        const uint32_t c4 = seg_codes[b4];
 #pragma unroll
-      for (int d = W / 2; d >= 1; d >>= 1) {
-        const double os = __shfl_xor(sc, d, W);
-        const uint32_t ok = (uint32_t)__shfl_xor((int)key, d, W);
-        if (os > sc || (os == sc && ok < key)) {
-          sc = os;
-          key = ok;
-        }
+        for (int u = 0; u < 4; ++u) acc += ((c4 >> (8 * u)) & 0xFFu) <= code ? seg_pv[4 * b4 + u] : 0ull;
       }
-      if (sc > best) {
-        best = sc;
-        best_cb = (c << 8) | key;
+      const uint32_t NL = packed_n(acc);
+      if (valid && NL < N) {
+        const int64_t SL = packed_s(acc, NL);
+        const double sc = split_score(SL, NL, S - SL, N - NL);
+        if (sc > best) {
+          best = sc;
+          best_ib = ((uint32_t)(i0 + i) << 8) | code;
+        }
       }
     }
     wave_lds_sync();
   }
+  // segment arg-max: the largest score, then the lowest candidate, then the lowest bin
+#pragma unroll
+  for (int d = W / 2; d >= 1; d >>= 1) {
+    const double os = __shfl_xor(best, d, W);
+    const uint32_t ob = (uint32_t)__shfl_xor((int)best_ib, d, W);
+    if (os > best || (os == best && ob < best_ib)) {
+      best = os;
+      best_ib = ob;
+    }
+  }
   const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
-  const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+  const uint32_t col = split ? cand[best_ib >> 8] : 0u, bin = best_ib & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
   small_finish<W>(x, k, node_ok, r, split, col, bin, left, w, wy);
 }
@@ -397,12 +400,14 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
   for (int i = lane; i < mtry; i += kWave) s_cand[i] = cand[i];
   wave_lds_sync();
 
+  // each lane keeps the best of the splits it scores (rank `lane` of every
+  // candidate) as (score, candidate index << 8 | bin); one arg-max at the end
   double best = -1.0;
-  uint32_t best_cb = 0xFFFFFFFFu;
+  int32_t best_ib = INT_MAX;
   uint32_t c_next = rfl(s_cand[0]);
   uint32_t code_next = valid ? rowp[c_next] : 0u;
   for (int i = 0; i < mtry; ++i) {
-    const uint32_t c = c_next, code = code_next;
+    const uint32_t code = code_next;
     if (i + 1 < mtry) {  // fetch the next column's codes while this one is scanned
       c_next = rfl(s_cand[i + 1]);
       code_next = valid ? rowp[c_next] : 0u;
@@ -435,17 +440,18 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
     const uint64_t V = wave_incl_scan<uint64_t>(v_i);
     const uint32_t NL = packed_n(V);
     const int64_t SL = packed_s(V, NL);
-    double sc = -1.0;
-    if ((uint32_t)lane + 1 < total) sc = split_score(SL, NL, S - SL, N - NL);
-    const ArgMax am = wave_argmax(sc, (int32_t)bin);
-    if (am.score > best) {
-      best = am.score;
-      best_cb = (c << 8) | (uint32_t)am.key;
+    if ((uint32_t)lane + 1 < total) {
+      const double sc = split_score(SL, NL, S - SL, N - NL);
+      if (sc > best) {
+        best = sc;
+        best_ib = (i << 8) | (int32_t)bin;
+      }
     }
     wave_lds_sync();
   }
-  const bool split = best >= 0.0 && best - parent_score(S, N) > 0.0;
-  const uint32_t col = best_cb >> 8, bin = best_cb & 0xFF;
+  const ArgMax am = wave_argmax(best, best_ib);
+  const bool split = am.score >= 0.0 && am.score - parent_score(S, N) > 0.0;
+  const uint32_t col = split ? (uint32_t)s_cand[am.key >> 8] : 0u, bin = (uint32_t)am.key & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
   const uint32_t NL = wave_sum(left ? w : 0u);
   const int64_t SL = wave_sum(left ? wy : (int64_t)0);
