@@ -65,7 +65,6 @@ struct Rec {
 // indexing, so that every pointer stays in scalar registers.
 struct Level2 {
   uint64_t* buf;
-  int32_t* slot;
   uint32_t* mstart;
   uint32_t* mend;
   uint32_t* mN;
@@ -86,6 +85,7 @@ struct Scratch {
   uint32_t* rank;
   uint32_t* curL;
   uint32_t* curR;
+  uint2* chunks;  // partition work: (split node, first entry) of every 64-entry chunk
   NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
   NodeDesc* big;
   NodeDesc* huge;
@@ -106,7 +106,6 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   Level2* lv[2] = {&s->L0, &s->L1};
   for (int b = 0; b < 2; ++b) {
     lv[b]->buf = reinterpret_cast<uint64_t*>(take(8 * n));
-    lv[b]->slot = reinterpret_cast<int32_t*>(take(4 * n));
     lv[b]->mstart = reinterpret_cast<uint32_t*>(take(4 * n));
     lv[b]->mend = reinterpret_cast<uint32_t*>(take(4 * n));
     lv[b]->mN = reinterpret_cast<uint32_t*>(take(4 * n));
@@ -123,6 +122,9 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
+  // a split node holds at least two rows, so a level has at most n/2 of them
+  // and at most n/64 + n/2 chunks
+  s->chunks = reinterpret_cast<uint2*>(take(sizeof(uint2) * (n / 64 + n / 2 + 2)));
   // class c holds nodes of more than 2 << c rows (c >= 1)
   for (int c = 0; c < kSegClasses; ++c)
     s->seg[c] = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * (n / (1 + (c ? (2u << c) : 0)) + 1)));
@@ -766,7 +768,6 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       const uint32_t row = train ? (uint32_t)train[i] : (uint32_t)i;
       const int64_t y = a.y_fp[row];
       sc.L0.buf[pos] = entry_pack(row, c, y);
-      sc.L0.slot[pos] = 0;
       N0 += c;
       S0 += (int64_t)c * y;
       Q0 += (uint64_t)((int64_t)c * y * y);
@@ -874,14 +875,18 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     // (d) decisions of the large nodes
     for (uint32_t j = tid; j < n_big; j += BLOCK) decide_from_recs(x, sc.big[j].k, sc.recs + (size_t)j * mtry, mtry);
     __syncthreads();
-    // (e) breadth-first child ids, node words, children's sums and cursors
-    uint32_t n_split = 0;
+    // (e) breadth-first child ids, node words, children's sums and cursors, and
+    // the partition's chunks of 64 entries of every split node
+    uint32_t n_split = 0, n_chunks = 0;
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
       const uint32_t k = b0 + tid;
       const bool in = k < level_cnt;
       const bool split = in && sc.status[k] == kSplit;
-      uint32_t total;
+      uint32_t total, ctotal;
       const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, sh.tmp, total) + n_split;
+      const uint32_t nch = split ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
+      const uint32_t cfirst = block_exscan<BLOCK>(nch, sh.tmp, ctotal) + n_chunks;
+      for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint2(k, x.mstart[k] + c * kWave);
       if (in) {
         const uint32_t node = level_lo + k;
         const uint32_t N = x.mN[k];
@@ -913,6 +918,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         a.node_N[base_node + node] = N;
       }
       n_split += total;
+      n_chunks += ctotal;
     }
     __syncthreads();
     if ((int64_t)next_id + 2 * (int64_t)n_split > T.capacity) {
@@ -920,54 +926,39 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       next_id = (uint32_t)T.capacity;
       break;
     }
-    // (f) partition the entries of split nodes into their children's segments;
-    // the lanes of a wave that send rows of one node to one side share a
-    // single cursor atomic, and take consecutive slots in lane order; the
-    // left side's sum of w y^2 is added up on the way
-    for (uint32_t b0 = 0; b0 < n_inbag; b0 += BLOCK) {
-      const uint32_t p = b0 + tid;
-      const int32_t k = p < n_inbag ? C.slot[p] : -1;
-      const bool mv = k >= 0 && sc.status[k] == kSplit;
+    // (f) partition the entries of split nodes into their children's segments,
+    // one wave per chunk of 64 entries of one node: the lanes that go left take
+    // consecutive slots from the left cursor in lane order, the others from
+    // the right cursor, one atomic each; the left side's sum of w y^2 is added
+    // up on the way.  Rows of leaves are not touched again.
+    for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
+      const uint2 cw = sc.chunks[ch];
+      const uint32_t k = rfl(cw.x), p0 = rfl(cw.y);
+      const uint32_t en = x.mend[k];
+      const uint32_t col = sc.dcol[k], bin = sc.dbin[k];
+      const uint32_t p = p0 + (uint32_t)lane;
+      const bool mv = p < en;
       uint64_t e = 0, wyy = 0;
-      uint32_t side = 0;
+      bool go_left = false;
       if (mv) {
         e = C.buf[p];
-        side = a.codes[(size_t)entry_row(e) * a.C + sc.dcol[k]] <= sc.dbin[k] ? 0u : 1u;
+        go_left = a.codes[(size_t)entry_row(e) * a.C + col] <= bin;
         const int64_t y = entry_y(e);
-        wyy = side ? 0ull : (uint64_t)((int64_t)entry_w(e) * y * y);
-      } else if (p < n_inbag) {
-        X.slot[p] = -1;
+        wyy = go_left ? (uint64_t)((int64_t)entry_w(e) * y * y) : 0ull;
       }
-      const int32_t key = mv ? (int32_t)(2 * k + side) : -1;
-      const uint64_t below_mask = (1ull << lane) - 1ull;
-      uint64_t todo = __ballot(mv);
-      uint32_t my_base = 0, my_rank = 0;
-      int my_leader = 0;
-      while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
-        const uint64_t peers = __ballot(key == lkey) & todo;
-        todo &= ~peers;
-        if (key == lkey) {
-          my_leader = leader;
-          my_rank = (uint32_t)__popcll(peers & below_mask);
-        }
-        if (lane == leader) {
-          const uint32_t cnt = (uint32_t)__popcll(peers);
-          const uint32_t kk = (uint32_t)lkey >> 1;
-          my_base = (lkey & 1) ? atomicSub(&sc.curR[kk], cnt) - cnt : atomicAdd(&sc.curL[kk], cnt);
-        }
-        if ((lkey & 1) == 0) {
-          const uint64_t q = wave_sum(key == lkey ? wyy : 0ull);
-          if (lane == leader) atomicAdd((unsigned long long*)&sc.qacc[(uint32_t)lkey >> 1], (unsigned long long)q);
-        }
+      const uint64_t lm = __ballot(mv && go_left), rm = __ballot(mv && !go_left);
+      const uint64_t below = (1ull << lane) - 1ull;
+      uint32_t bl = 0, br = 0;
+      if (lane == 0) {
+        const uint32_t nl = (uint32_t)__popcll(lm), nr = (uint32_t)__popcll(rm);
+        if (nl) bl = atomicAdd(&sc.curL[k], nl);
+        if (nr) br = atomicSub(&sc.curR[k], nr) - nr;
       }
-      const uint32_t base = (uint32_t)__shfl((int)my_base, my_leader, kWave);
-      if (mv) {
-        const uint32_t dst = base + my_rank;
-        X.buf[dst] = e;
-        X.slot[dst] = (int32_t)(2 * sc.rank[k] + side);
-      }
+      bl = (uint32_t)__shfl((int)bl, 0, kWave);
+      br = (uint32_t)__shfl((int)br, 0, kWave);
+      if (mv) X.buf[go_left ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e;
+      const uint64_t q = wave_sum(wyy);
+      if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&sc.qacc[k], (unsigned long long)q);
     }
     __syncthreads();
     // (g) the boundary between each pair of children, and their sums of w y^2
