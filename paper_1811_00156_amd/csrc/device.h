@@ -111,37 +111,72 @@ __device__ __forceinline__ double parent_score(int64_t S, uint64_t N) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+// The collectives below move values between lanes with DPP row operations
+// (GFX9 encoding) instead of LDS permutes, and must be called with every lane
+// of the wave active.  A wave64 inclusive scan is a Kogge-Stone scan inside each
+// row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast:15 adds row 0's total
+// into row 1 and row 2's into row 3, and row_bcast:31 adds the first two rows'
+// total into rows 2 and 3.  A lane whose source is outside its row, or in a
+// row the row mask leaves out, receives the operation's identity.
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t identity, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t identity, uint64_t v) {
+  const uint32_t lo = dpp32<CTRL, ROW_MASK>((uint32_t)identity, (uint32_t)v);
+  const uint32_t hi = dpp32<CTRL, ROW_MASK>((uint32_t)(identity >> 32), (uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+  if constexpr (sizeof(T) == 8)
+    return (T)dpp64<CTRL, ROW_MASK>(0ull, (uint64_t)v);
+  else
+    return (T)dpp32<CTRL, ROW_MASK>(0u, (uint32_t)v);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = (int)lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-
+// Inclusive prefix sum over the wave's lanes (integer T of 4 or 8 bytes).
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-  const int lane = (int)lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const T o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
+  v += dpp_move<kDppRowShr1, 0xf>(v);
+  v += dpp_move<kDppRowShr2, 0xf>(v);
+  v += dpp_move<kDppRowShr4, 0xf>(v);
+  v += dpp_move<kDppRowShr8, 0xf>(v);
+  v += dpp_move<kDppRowBcast15, 0xa>(v);
+  v += dpp_move<kDppRowBcast31, 0xc>(v);
   return v;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) { return wave_incl_scan<uint32_t>(v); }
+
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int l) {
+  if constexpr (sizeof(T) == 8) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (T)(((uint64_t)hi << 32) | lo);
+  } else {
+    return (T)__builtin_amdgcn_readlane((int)v, l);
+  }
+}
+
+// Sum over the wave (integer T), in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  return read_lane(wave_incl_scan<T>(v), kWave - 1);
 }
 
 // Arg-max of (score, key) over the wave: the largest score, then the smallest
 // key.  Every lane returns the winner and the lane that holds it (lowest lane
-// among equals).
+// among equals).  A prefix arg-max with the scan's DPP pattern leaves the
+// wave's winner in the last lane.
 struct ArgMax {
   double score;
   int32_t key;
@@ -152,20 +187,31 @@ __device__ __forceinline__ bool argmax_better(double s1, int32_t k1, int32_t l1,
   if (k1 != k2) return k1 < k2;
   return l1 < l2;
 }
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void argmax_step(ArgMax& m) {
+  constexpr uint64_t kMinusInf = 0xFFF0000000000000ull;
+  const double s = __builtin_bit_cast(double, dpp64<CTRL, ROW_MASK>(kMinusInf, __builtin_bit_cast(uint64_t, m.score)));
+  const int32_t k = (int32_t)dpp32<CTRL, ROW_MASK>(0x7FFFFFFFu, (uint32_t)m.key);
+  const int32_t l = (int32_t)dpp32<CTRL, ROW_MASK>(0x7FFFFFFFu, (uint32_t)m.lane);
+  if (argmax_better(s, k, l, m.score, m.key, m.lane)) {
+    m.score = s;
+    m.key = k;
+    m.lane = l;
+  }
+}
 __device__ __forceinline__ ArgMax wave_argmax(double score, int32_t key) {
   ArgMax m{score, key, (int32_t)lane_id()};
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const double s = __shfl_xor(m.score, d, kWave);
-    const int32_t k = __shfl_xor(m.key, d, kWave);
-    const int32_t l = __shfl_xor(m.lane, d, kWave);
-    if (argmax_better(s, k, l, m.score, m.key, m.lane)) {
-      m.score = s;
-      m.key = k;
-      m.lane = l;
-    }
-  }
-  return m;
+  argmax_step<kDppRowShr1, 0xf>(m);
+  argmax_step<kDppRowShr2, 0xf>(m);
+  argmax_step<kDppRowShr4, 0xf>(m);
+  argmax_step<kDppRowShr8, 0xf>(m);
+  argmax_step<kDppRowBcast15, 0xa>(m);
+  argmax_step<kDppRowBcast31, 0xc>(m);
+  ArgMax r;
+  r.score = __builtin_bit_cast(double, read_lane(__builtin_bit_cast(uint64_t, m.score), kWave - 1));
+  r.key = read_lane(m.key, kWave - 1);
+  r.lane = read_lane(m.lane, kWave - 1);
+  return r;
 }
 
 // Make this wave's LDS writes visible to its other lanes.

@@ -886,12 +886,17 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, sh.tmp, total) + n_split;
       const uint32_t nch = split ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
       const uint32_t cfirst = block_exscan<BLOCK>(nch, sh.tmp, ctotal) + n_chunks;
-      for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint2(k, x.mstart[k] + c * kWave);
+      // (the bounds below hold by construction; the guards keep a broken
+      // invariant from writing outside the scratch arrays)
+      if ((uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2))
+        for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint2(k, x.mstart[k] + c * kWave);
       if (in) {
         const uint32_t node = level_lo + k;
         const uint32_t N = x.mN[k];
         const int64_t S = x.mS[k];
-        if (split) {
+        if (split && (int64_t)2 * r + 1 >= a.n_cap) {
+          atomicOr(a.status, kStatusCapacity);
+        } else if (split) {
           const uint32_t left = next_id + 2 * r;
           if ((int64_t)left + 1 < T.capacity) {
             a.nodes[base_node + node] = node_split(sc.dcol[k], sc.dbin[k], left);
@@ -921,8 +926,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       n_chunks += ctotal;
     }
     __syncthreads();
-    if ((int64_t)next_id + 2 * (int64_t)n_split > T.capacity) {
+    if ((int64_t)next_id + 2 * (int64_t)n_split > T.capacity ||
+        (int64_t)n_chunks > a.n_cap / 64 + a.n_cap / 2 + 2) {
       // cannot happen for consistent inputs: every child holds an in-bag row
+      if (tid == 0) atomicOr(a.status, kStatusCapacity);
       next_id = (uint32_t)T.capacity;
       break;
     }
@@ -954,8 +961,8 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         if (nl) bl = atomicAdd(&sc.curL[k], nl);
         if (nr) br = atomicSub(&sc.curR[k], nr) - nr;
       }
-      bl = (uint32_t)__shfl((int)bl, 0, kWave);
-      br = (uint32_t)__shfl((int)br, 0, kWave);
+      bl = read_lane(bl, 0);
+      br = read_lane(br, 0);
       if (mv) X.buf[go_left ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e;
       const uint64_t q = wave_sum(wyy);
       if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&sc.qacc[k], (unsigned long long)q);
