@@ -214,6 +214,60 @@ __device__ __forceinline__ ArgMax wave_argmax(double score, int32_t key) {
   return r;
 }
 
+// All-reductions inside aligned segments of W = 4, 8, 16 or 32 lanes, for an
+// operation that is associative and commutative.  Within a row of 16 the steps
+// are DPP permutations (every source lane valid): a rotation by 8 pairs lanes
+// i and i ^ 8, the half-row mirror pairs i and 7 - i of each group of 8, and
+// two quad permutations pair i ^ 2 and i ^ 1; for any W the combined sets of
+// each lane cover its segment exactly once.  The 16-lane step of W = 32 is one
+// LDS permute.
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowRor8 = 0x128;
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_perm(T v) {
+  return dpp_move<CTRL, 0xf>(v);
+}
+template <int W, typename T>
+__device__ __forceinline__ T seg_sum(T v) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32, "segment width");
+  if constexpr (W == 32) v += __shfl_xor(v, 16, kWave);
+  if constexpr (W >= 16) v += dpp_perm<kDppRowRor8>(v);
+  if constexpr (W >= 8) v += dpp_perm<kDppHalfMirror>(v);
+  v += dpp_perm<kDppQuadXor2>(v);
+  v += dpp_perm<kDppQuadXor1>(v);
+  return v;
+}
+
+// Segment arg-max of (score, key): the largest score, then the smallest key.
+template <int CTRL>
+__device__ __forceinline__ void seg_argmax_step(double& s, uint32_t& k) {
+  const double os = __builtin_bit_cast(double, dpp_perm<CTRL>(__builtin_bit_cast(uint64_t, s)));
+  const uint32_t ok = dpp_perm<CTRL>(k);
+  if (os > s || (os == s && ok < k)) {
+    s = os;
+    k = ok;
+  }
+}
+template <int W>
+__device__ __forceinline__ void seg_argmax(double& s, uint32_t& k) {
+  static_assert(W == 4 || W == 8 || W == 16 || W == 32, "segment width");
+  if constexpr (W == 32) {
+    const double os = __shfl_xor(s, 16, kWave);
+    const uint32_t ok = (uint32_t)__shfl_xor((int)k, 16, kWave);
+    if (os > s || (os == s && ok < k)) {
+      s = os;
+      k = ok;
+    }
+  }
+  if constexpr (W >= 16) seg_argmax_step<kDppRowRor8>(s, k);
+  if constexpr (W >= 8) seg_argmax_step<kDppHalfMirror>(s, k);
+  seg_argmax_step<kDppQuadXor2>(s, k);
+  seg_argmax_step<kDppQuadXor1>(s, k);
+}
+
 // Make this wave's LDS writes visible to its other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

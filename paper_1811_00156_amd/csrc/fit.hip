@@ -275,13 +275,9 @@ __device__ __forceinline__ int64_t packed_s(uint64_t v, uint32_t n) { return (in
 template <int W>
 __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node_ok, int r, bool split, uint32_t col,
                                              uint32_t bin, bool left, uint32_t w, int64_t wy) {
-  uint32_t NL = left ? w : 0u;
-  int64_t SL = left ? wy : 0;
-#pragma unroll
-  for (int d = W / 2; d >= 1; d >>= 1) {
-    NL += (uint32_t)__shfl_xor((int)NL, d, W);
-    SL += __shfl_xor(SL, d, W);
-  }
+  const uint64_t acc = seg_sum<W>(left ? pack_ns(w, wy) : 0ull);
+  const uint32_t NL = packed_n(acc);
+  const int64_t SL = packed_s(acc, NL);
   if (node_ok && r == 0) {
     if (split) {
       x.sc.dcol[k] = (uint8_t)col;
@@ -357,15 +353,7 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
     wave_lds_sync();
   }
   // segment arg-max: the largest score, then the lowest candidate, then the lowest bin
-#pragma unroll
-  for (int d = W / 2; d >= 1; d >>= 1) {
-    const double os = __shfl_xor(best, d, W);
-    const uint32_t ob = (uint32_t)__shfl_xor((int)best_ib, d, W);
-    if (os > best || (os == best && ob < best_ib)) {
-      best = os;
-      best_ib = ob;
-    }
-  }
+  seg_argmax<W>(best, best_ib);
   const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
   const uint32_t col = split ? cand[best_ib >> 8] : 0u, bin = best_ib & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
