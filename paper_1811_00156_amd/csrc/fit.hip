@@ -580,138 +580,159 @@ struct Shared {
   uint64_t red[16];
   uint32_t cnt[3 + kSegClasses];  // [1] large, [2] wide, [3..] small nodes per segment width
   uint32_t task;
-  // the wide batch being searched: node j's level index, first entry, rows,
-  // first chunk, weight and sum
-  uint32_t wk[kWideMax], wstart[kWideMax], wlen[kWideMax], wcpre[kWideMax], wN[kWideMax];
-  int64_t wS[kWideMax];
-  alignas(8) uint8_t cand[256];  // wide node j's candidate i at j * round_up(mtry, 8) + i
-  Rec recs[256];      // node j's record of candidate i at j * mtry + i
+  // two wide batches (the one being searched and the next): node j's first
+  // entry, rows, first chunk, weight, sum, and its candidates at
+  // j * round_up(mtry, 8) + i
+  uint32_t wstart[2][kWideMax], wlen[2][kWideMax], wcpre[2][kWideMax], wN[2][kWideMax];
+  int64_t wS[2][kWideMax];
+  alignas(8) uint8_t cand[2][256];
 };
 
-// A batch of nb wide nodes.  Node j's rows are cut into chunks of 64, one
-// wave per chunk, so the candidate columns are uniform across a wave.  Each
-// lane reads its row's entry once and, when the padded code rows fit 80 bytes,
-// the whole code row with five 16-byte loads; the candidate codes are then
-// picked from registers and each is added to the packed bin of its (node,
-// column) histogram (hc columns at a time when they do not all fit the LDS).
-// One wave per (node, column) then scans, and the nodes are decided from the
-// per-column records.
+// Metadata of wide batch `bi` (nodes list[0 .. nb)) into buffer bi & 1.
 template <int BLOCK>
-__device__ void wide_batch(const Ctx& x, const NodeDesc* list, int nb, int hc, uint8_t* lds, Shared& sh) {
-  constexpr int NW = BLOCK / kWave;
-  const GrowArgs& a = *x.a;
-  const int mtry = x.T->mtry;
-  const int bs = a.bstride;
-  const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
-  uint64_t* H = reinterpret_cast<uint64_t*>(lds);
-  uint32_t cpre[kWideMax];  // first chunk of node j (uniform)
-  uint32_t n_chunks = 0;
-#pragma unroll
-  for (int j = 0; j < kWideMax; ++j) {
-    cpre[j] = n_chunks;
-    n_chunks += j < nb ? (list[j].len + kWave - 1) / kWave : 0u;
-  }
+__device__ __forceinline__ void wide_setup(const Ctx& x, const NodeDesc* list, int nb, int bi, Shared& sh) {
+  const int mtry = x.T->mtry, tid = threadIdx.x, q = bi & 1;
   if (tid < nb) {
     const NodeDesc d = list[tid];
-    sh.wk[tid] = d.k;
-    sh.wstart[tid] = d.start;
-    sh.wlen[tid] = d.len;
-    sh.wN[tid] = d.N;
-    sh.wS[tid] = d.S;
-#pragma unroll
-    for (int j = 0; j < kWideMax; ++j)
-      if (j == tid) sh.wcpre[j] = cpre[j];
+    uint32_t first = 0;
+    for (int j = 0; j < tid; ++j) first += (list[j].len + kWave - 1) / kWave;
+    sh.wstart[q][tid] = d.start;
+    sh.wlen[q][tid] = d.len;
+    sh.wcpre[q][tid] = first;
+    sh.wN[q][tid] = d.N;
+    sh.wS[q][tid] = d.S;
   }
   // candidates padded to 8 per node (with the node's last one), read 8 at a time
   const int cst = (mtry + 7) & ~7;
   for (int i = tid; i < nb * cst; i += BLOCK)
-    sh.cand[i] = x.sc.cand[(size_t)list[i / cst].k * mtry + min(i % cst, mtry - 1)];
-  __syncthreads();
-  // node of chunk ch: the number of later nodes' first chunks <= ch
-  auto node_of = [&](uint32_t ch) {
-    int j = 0;
-#pragma unroll
-    for (int jj = 1; jj < kWideMax; ++jj) j += (jj < nb && ch >= cpre[jj]) ? 1 : 0;
-    return j;
-  };
+    sh.cand[q][i] = x.sc.cand[(size_t)list[i / cst].k * mtry + min(i % cst, mtry - 1)];
+}
+
+// The wide nodes of a level, nb at a time.  Node j of a batch has its rows cut
+// into chunks of 64, one wave per chunk, so the candidate columns are uniform
+// across a wave.  Each lane reads its row's entry once and, when the padded
+// code rows fit 80 bytes, the whole code row with five 16-byte loads; the
+// candidate codes are picked from registers and each is added to the packed
+// bin of its (node, column) histogram (hc columns at a time when they do not
+// all fit the LDS).  One wave per (node, column) then scans, writes the
+// column's record (decided with the other nodes' after the phase) and zeroes
+// the bins it read, while the next batch's metadata is staged.
+template <int BLOCK>
+__device__ void wide_phase(const Ctx& x, const NodeDesc* list, uint32_t n_wide, int nb_max, int hc, uint32_t rec_base,
+                           uint8_t* lds, Shared& sh) {
+  constexpr int NW = BLOCK / kWave;
+  const GrowArgs& a = *x.a;
+  const int mtry = x.T->mtry;
+  const int bs = a.bstride;
+  const int cst = (mtry + 7) & ~7;
+  const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
+  uint64_t* H = reinterpret_cast<uint64_t*>(lds);
   const bool row_regs = a.Cp <= 80;
-  for (int c0 = 0; c0 < mtry; c0 += hc) {
-    const int nc = min(hc, mtry - c0);
-    const int words = nb * nc * bs;
-    for (int i = 2 * tid; i < words; i += 2 * BLOCK) *reinterpret_cast<uint4*>(H + i) = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
-    for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
-      const int j = node_of(ch);
-      const uint32_t r = (ch - sh.wcpre[j]) * kWave + (uint32_t)lane;
-      const bool valid = r < sh.wlen[j];
-      uint64_t v = 0;
-      uint32_t row = 0;
-      if (valid) {
-        const uint64_t e = x.buf[sh.wstart[j] + r];
-        const uint32_t w = entry_w(e);
-        v = pack_ns(w, (int64_t)w * entry_y(e));
-        row = entry_row(e);
-      }
-      const uint8_t* cj = sh.cand + j * cst + c0;
-      uint64_t* Hj = H + (size_t)j * nc * bs;
-      if (row_regs) {
-        // five unconditional loads: the padded copy has 64 bytes of slack after
-        // its last row, and a lane without a row reads row 0
-        uint32_t rw[20];
-        const uint4* rp = reinterpret_cast<const uint4*>(a.codes_p + (size_t)row * a.Cp);
+  // the histograms start zeroed; each scan zeroes what it read
+  for (uint32_t i = 2 * tid; i < a.union_bytes / 8; i += 2 * BLOCK)
+    *reinterpret_cast<uint4*>(H + i) = make_uint4(0u, 0u, 0u, 0u);
+  wide_setup<BLOCK>(x, list, (int)min((uint32_t)nb_max, n_wide), 0, sh);
+  __syncthreads();
+  int bi = 0;
+  for (uint32_t h0 = 0; h0 < n_wide; h0 += (uint32_t)nb_max, ++bi) {
+    const int nb = (int)min((uint32_t)nb_max, n_wide - h0);
+    const NodeDesc* bl = list + h0;
+    const int q = bi & 1;
+    uint32_t cpre[kWideMax];  // first chunk of node j (uniform)
+    uint32_t n_chunks = 0;
 #pragma unroll
-        for (int u = 0; u < 5; ++u) {
-          const uint4 t = rp[u];
-          rw[4 * u] = t.x;
-          rw[4 * u + 1] = t.y;
-          rw[4 * u + 2] = t.z;
-          rw[4 * u + 3] = t.w;
+    for (int j = 0; j < kWideMax; ++j) {
+      cpre[j] = n_chunks;
+      n_chunks += j < nb ? (bl[j].len + kWave - 1) / kWave : 0u;
+    }
+    // node of chunk ch: the number of later nodes' first chunks <= ch
+    auto node_of = [&](uint32_t ch) {
+      int j = 0;
+#pragma unroll
+      for (int jj = 1; jj < kWideMax; ++jj) j += (jj < nb && ch >= cpre[jj]) ? 1 : 0;
+      return j;
+    };
+    for (int c0 = 0; c0 < mtry; c0 += hc) {
+      const int nc = min(hc, mtry - c0);
+      for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
+        const int j = node_of(ch);
+        const uint32_t r = (ch - sh.wcpre[q][j]) * kWave + (uint32_t)lane;
+        const bool valid = r < sh.wlen[q][j];
+        uint64_t v = 0;
+        uint32_t row = 0;
+        if (valid) {
+          const uint64_t e = x.buf[sh.wstart[q][j] + r];
+          const uint32_t w = entry_w(e);
+          v = pack_ns(w, (int64_t)w * entry_y(e));
+          row = entry_row(e);
         }
-        for (int i0 = 0; i0 < nc; i0 += 8) {
-          const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
-          const uint32_t lo = rfl((uint32_t)c8), hi = rfl((uint32_t)(c8 >> 32));
+        const uint8_t* cj = sh.cand[q] + j * cst + c0;
+        uint64_t* Hj = H + (size_t)j * nc * bs;
+        if (row_regs) {
+          // five unconditional loads: the padded copy has 64 bytes of slack after
+          // its last row, and a lane without a row reads row 0
+          uint32_t rw[20];
+          const uint4* rp = reinterpret_cast<const uint4*>(a.codes_p + (size_t)row * a.Cp);
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const uint32_t col = ((u < 4 ? lo : hi) >> (8 * (u & 3))) & 0xFFu;
-            const uint32_t code = (rw[col >> 2] >> (8 * (col & 3))) & 0xFFu;
-            if (valid && i0 + u < nc)
-              atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)code], (unsigned long long)v);
+          for (int u = 0; u < 5; ++u) {
+            const uint4 t = rp[u];
+            rw[4 * u] = t.x;
+            rw[4 * u + 1] = t.y;
+            rw[4 * u + 2] = t.z;
+            rw[4 * u + 3] = t.w;
+          }
+          for (int i0 = 0; i0 < nc; i0 += 8) {
+            const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
+            const uint32_t lo = rfl((uint32_t)c8), hi = rfl((uint32_t)(c8 >> 32));
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const uint32_t col = ((u < 4 ? lo : hi) >> (8 * (u & 3))) & 0xFFu;
+              const uint32_t code = (rw[col >> 2] >> (8 * (col & 3))) & 0xFFu;
+              if (valid && i0 + u < nc)
+                atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)code], (unsigned long long)v);
+            }
+          }
+        } else {
+          const uint8_t* rp = a.codes + (size_t)row * a.C;
+          for (int i0 = 0; i0 < nc; i0 += 8) {
+            const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
+            uint32_t cd[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cd[u] = valid ? rp[(uint32_t)(c8 >> (8 * u)) & 0xFFu] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (valid && i0 + u < nc)
+                atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)cd[u]], (unsigned long long)v);
           }
         }
-      } else {
-        const uint8_t* rp = a.codes + (size_t)row * a.C;
-        for (int i0 = 0; i0 < nc; i0 += 8) {
-          const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
-          uint32_t cd[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) cd[u] = valid ? rp[(uint32_t)(c8 >> (8 * u)) & 0xFFu] : 0u;
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (valid && i0 + u < nc)
-              atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)cd[u]], (unsigned long long)v);
+      }
+      __syncthreads();
+      for (int t = wid; t < nb * nc; t += NW) {
+        const int j = t / nc, i = t % nc;
+        const int c = sh.cand[q][j * cst + c0 + i];
+        const int B = a.n_bins[c];
+        uint64_t* hv = H + (size_t)t * bs;
+        uint32_t NL;
+        int64_t SL;
+        const ArgMax am = scan_packed(hv, B, sh.wN[q][j], sh.wS[q][j], NL, SL);
+        if (lane == am.lane) {
+          Rec rc;
+          rc.score = am.score;
+          rc.SL = SL;
+          rc.NL = NL;
+          rc.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
+          x.sc.recs[(size_t)(rec_base + h0 + j) * mtry + c0 + i] = rc;
         }
+        // zero the bins this lane read (lane l scans bins 4l .. 4l + 3)
+        if (4 * lane < B) *reinterpret_cast<uint4*>(hv + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+        if (4 * lane + 2 < B) *reinterpret_cast<uint4*>(hv + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
       }
+      // the next batch's metadata goes to the other buffer meanwhile
+      if (c0 + hc >= mtry && h0 + (uint32_t)nb_max < n_wide)
+        wide_setup<BLOCK>(x, list + h0 + nb_max, (int)min((uint32_t)nb_max, n_wide - h0 - nb_max), bi + 1, sh);
+      __syncthreads();
     }
-    __syncthreads();
-    for (int t = wid; t < nb * nc; t += NW) {
-      const int j = t / nc, i = t % nc;
-      const int c = sh.cand[j * cst + c0 + i];
-      uint32_t NL;
-      int64_t SL;
-      const ArgMax am = scan_packed(H + (size_t)t * bs, a.n_bins[c], sh.wN[j], sh.wS[j], NL, SL);
-      if (lane == am.lane) {
-        Rec r;
-        r.score = am.score;
-        r.SL = SL;
-        r.NL = NL;
-        r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
-        sh.recs[j * mtry + c0 + i] = r;
-      }
-    }
-    __syncthreads();
   }
-  if (tid < nb) decide_from_recs(x, sh.wk[tid], sh.recs + tid * mtry, mtry);
-  __syncthreads();
 }
 
 // WIDE: the launch may hold nodes above the wide limit (the kernel without
@@ -829,10 +850,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       int nb = 1, hc = mtry;
       if (per_node <= (int)a.union_bytes)
         nb = min(min(kWideMax, 256 / ((mtry + 7) & ~7)), (int)a.union_bytes / per_node);
+      // (records of wide node j go after the large nodes', at n_big + j)
       else  // column chunks of a multiple of 8 (the LDS holds at least 8 columns)
         hc = max(8, (int)a.union_bytes / (a.bstride * 8) / 8 * 8);
-      for (uint32_t h0 = 0; h0 < n_huge; h0 += (uint32_t)nb)
-        wide_batch<BLOCK>(x, sc.huge + h0, (int)min((uint32_t)nb, n_huge - h0), hc, lds, sh);
+      wide_phase<BLOCK>(x, sc.huge, n_huge, nb, hc, n_big, lds, sh);
     }
     // (c) large-node columns and small-node segments, one wave each
     {
@@ -860,8 +881,9 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       }
     }
     __syncthreads();
-    // (d) decisions of the large nodes
-    for (uint32_t j = tid; j < n_big; j += BLOCK) decide_from_recs(x, sc.big[j].k, sc.recs + (size_t)j * mtry, mtry);
+    // (d) decisions of the large and the wide nodes
+    for (uint32_t j = tid; j < n_big + (WIDE ? n_huge : 0u); j += BLOCK)
+      decide_from_recs(x, j < n_big ? sc.big[j].k : sc.huge[j - n_big].k, sc.recs + (size_t)j * mtry, mtry);
     __syncthreads();
     // (e) breadth-first child ids, node words, children's sums and cursors, and
     // the partition's chunks of 64 entries of every split node
