@@ -948,34 +948,48 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     // consecutive slots from the left cursor in lane order, the others from
     // the right cursor, one atomic each; the left side's sum of w y^2 is added
     // up on the way.  Rows of leaves are not touched again.
-    for (uint32_t ch = (uint32_t)wid; ch < n_chunks; ch += NW) {
-      const uint2 cw = sc.chunks[ch];
-      const uint32_t k = rfl(cw.x), p0 = rfl(cw.y);
-      const uint32_t en = x.mend[k];
-      const uint32_t col = sc.dcol[k], bin = sc.dbin[k];
-      const uint32_t p = p0 + (uint32_t)lane;
-      const bool mv = p < en;
-      uint64_t e = 0, wyy = 0;
-      bool go_left = false;
-      if (mv) {
-        e = C.buf[p];
-        go_left = a.codes[(size_t)entry_row(e) * a.C + col] <= bin;
-        const int64_t y = entry_y(e);
-        wyy = go_left ? (uint64_t)((int64_t)entry_w(e) * y * y) : 0ull;
+    // Four chunks per wave are in flight at a time, so that their dependent
+    // loads (chunk, node, entry, code) overlap.
+    constexpr int UP = 4;
+    for (uint32_t c0 = (uint32_t)wid; c0 < n_chunks; c0 += UP * NW) {
+      uint32_t k[UP], en[UP], col[UP], bin[UP];
+      uint64_t e[UP];
+      bool mv[UP], go_left[UP];
+#pragma unroll
+      for (int u = 0; u < UP; ++u) {
+        const uint32_t ch = c0 + (uint32_t)(u * NW);
+        const uint2 cw = ch < n_chunks ? sc.chunks[ch] : make_uint2(0u, 0xFFFFFFFFu);
+        k[u] = rfl(cw.x);
+        const uint32_t p0 = rfl(cw.y);
+        en[u] = ch < n_chunks ? x.mend[k[u]] : 0u;
+        col[u] = sc.dcol[k[u]];
+        bin[u] = sc.dbin[k[u]];
+        const uint32_t p = p0 + (uint32_t)lane;
+        mv[u] = ch < n_chunks && p < en[u];
+        e[u] = mv[u] ? C.buf[p] : 0ull;
       }
-      const uint64_t lm = __ballot(mv && go_left), rm = __ballot(mv && !go_left);
-      const uint64_t below = (1ull << lane) - 1ull;
-      uint32_t bl = 0, br = 0;
-      if (lane == 0) {
-        const uint32_t nl = (uint32_t)__popcll(lm), nr = (uint32_t)__popcll(rm);
-        if (nl) bl = atomicAdd(&sc.curL[k], nl);
-        if (nr) br = atomicSub(&sc.curR[k], nr) - nr;
+#pragma unroll
+      for (int u = 0; u < UP; ++u)
+        go_left[u] = mv[u] && a.codes[(size_t)entry_row(e[u]) * a.C + col[u]] <= bin[u];
+#pragma unroll
+      for (int u = 0; u < UP; ++u) {
+        if (c0 + (uint32_t)(u * NW) >= n_chunks) break;
+        const uint64_t lm = __ballot(go_left[u]), rm = __ballot(mv[u] && !go_left[u]);
+        const uint64_t below = (1ull << lane) - 1ull;
+        uint32_t bl = 0, br = 0;
+        if (lane == 0) {
+          const uint32_t nl = (uint32_t)__popcll(lm), nr = (uint32_t)__popcll(rm);
+          if (nl) bl = atomicAdd(&sc.curL[k[u]], nl);
+          if (nr) br = atomicSub(&sc.curR[k[u]], nr) - nr;
+        }
+        bl = read_lane(bl, 0);
+        br = read_lane(br, 0);
+        if (mv[u])
+          X.buf[go_left[u] ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e[u];
+        const int64_t y = entry_y(e[u]);
+        const uint64_t q = wave_sum(go_left[u] ? (uint64_t)((int64_t)entry_w(e[u]) * y * y) : 0ull);
+        if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&sc.qacc[k[u]], (unsigned long long)q);
       }
-      bl = read_lane(bl, 0);
-      br = read_lane(br, 0);
-      if (mv) X.buf[go_left ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e;
-      const uint64_t q = wave_sum(wyy);
-      if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&sc.qacc[k], (unsigned long long)q);
     }
     __syncthreads();
     // (g) the boundary between each pair of children, and their sums of w y^2
