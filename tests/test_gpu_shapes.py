@@ -91,3 +91,34 @@ def test_wide_batches_in_column_chunks(block):
                 os.environ[k] = v
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"wide chunks block {block} tree {t}")
+
+
+@pytest.mark.parametrize("block,huge_min", [("256", "64"), ("1024", "64"), ("512", "100000")])
+def test_wide_code_rows_and_many_candidates(block, huge_min):
+    """100 features (code rows wider than 80 bytes, so the wide batches gather
+    codes byte by byte) and mtry 90 (more candidates than one 64-column staging
+    chunk of the small-node tasks), against the oracle."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    log(f"wide rows block={block} huge_min={huge_min}")
+    ds = synth.small(n_vec=700, n_devices=5, p_ln=60, p_u=40, seed=41)  # 3500 rows, 101 code columns
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 256)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 3, 90, 1, seed=6)
+    old = {k: os.environ.get(k) for k in ("AIWC_RF_GROW_BLOCK", "AIWC_RF_HUGE_MIN")}
+    os.environ.update({"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": huge_min})
+    try:
+        f = rf.aiwc_rf_fit(to_dev(ob.codes), rf.aiwc_rf_binner_from_counts(ob.n_bins), to_dev(ds.y),
+                           rf.make_params(3, 90, 1, True, 6))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"wide rows block {block} huge_min {huge_min} tree {t}")
