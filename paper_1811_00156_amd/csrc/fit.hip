@@ -72,11 +72,16 @@ struct Level2 {
   uint64_t* mQ;
 };
 
+// A node's candidate list takes mtry bytes rounded up to 16 (the padding
+// repeats the last candidate), so that it can be read with 16-byte loads.
+__host__ __device__ inline int cand_stride(int mtry) { return (mtry + 15) & ~15; }
+
 struct Scratch {
   uint32_t* cnt;
   Level2 L0, L1;
   uint8_t* status;
-  uint8_t* cand;  // level node k's candidate columns at k * mtry, ascending
+  uint8_t* cand;     // level node k's candidate columns at k * cand_stride(mtry), ascending, padded
+  uint32_t* btask;   // large node j's candidate i at j * mtry + i: column | bin count << 8
   uint8_t* dcol;
   uint8_t* dbin;
   uint32_t* dNL;
@@ -113,7 +118,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
     lv[b]->mQ = reinterpret_cast<uint64_t*>(take(8 * n));
   }
   s->status = reinterpret_cast<uint8_t*>(take(n));
-  s->cand = reinterpret_cast<uint8_t*>(take(n * (size_t)mtry_max));
+  s->cand = reinterpret_cast<uint8_t*>(take(n * (size_t)cand_stride(mtry_max)));
   s->dcol = reinterpret_cast<uint8_t*>(take(n));
   s->dbin = reinterpret_cast<uint8_t*>(take(n));
   s->dNL = reinterpret_cast<uint32_t*>(take(4 * n));
@@ -131,6 +136,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->big = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
   s->huge = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
+  s->btask = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n_large * (size_t)mtry_max));
   return off;
 }
 
@@ -240,6 +246,8 @@ __device__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t 
   for (uint64_t m = m1; m; m &= m - 1) out[i++] = (uint8_t)(64 + __builtin_ctzll(m));
   for (uint64_t m = m2; m; m &= m - 1) out[i++] = (uint8_t)(128 + __builtin_ctzll(m));
   for (uint64_t m = m3; m; m &= m - 1) out[i++] = (uint8_t)(192 + __builtin_ctzll(m));
+  const uint8_t last = out[mtry - 1];
+  for (; i < cand_stride(mtry); ++i) out[i] = last;
 }
 
 struct Ctx {
@@ -316,7 +324,7 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   uint8_t* s_codes = area + 512;                       // [64 columns][64 lanes]
   s_pv[lane] = pack_ns(w, wy);
   const uint8_t* rowp = a.codes + (size_t)row * a.C;
-  const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
+  const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
 
   // each lane keeps its own best split (score, candidate index, bin) over the
   // candidates in order; one segment arg-max at the end picks the node's
@@ -325,9 +333,18 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
   const uint64_t* seg_pv = s_pv + sbase;
   for (int i0 = 0; i0 < mtry; i0 += kWave) {
     const int nc = min(kWave, mtry - i0);
-    // gather the row's codes in every candidate column of this chunk at once
-#pragma unroll 8
-    for (int i = 0; i < nc; ++i) s_codes[i * kWave + lane] = valid ? rowp[node_ok ? cand[i0 + i] : 0] : 0;
+    // gather the row's codes in every candidate column of this chunk at once:
+    // sixteen candidates per 16-byte load, sixteen gathers in flight
+    for (int g0 = 0; g0 < nc; g0 += 16) {
+      const uint4 c16 = *reinterpret_cast<const uint4*>(cand + i0 + g0);
+      const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
+      uint32_t cd[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) cd[u] = valid ? rowp[(cw[u >> 2] >> (8 * (u & 3))) & 0xFFu] : 0u;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (g0 + u < nc) s_codes[(g0 + u) * kWave + lane] = (uint8_t)cd[u];
+    }
     wave_lds_sync();
     for (int i = 0; i < nc; ++i) {
       const uint8_t* col_codes = s_codes + i * kWave;
@@ -380,7 +397,7 @@ __device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32
   const int64_t wy = (int64_t)w * y;
   const uint64_t pv = pack_ns(w, wy);
   const uint8_t* rowp = a.codes + (size_t)entry_row(e) * a.C;
-  const uint8_t* cand = x.sc.cand + (size_t)k * mtry;
+  const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
   uint64_t* hv = reinterpret_cast<uint64_t*>(area);            // [256] packed bins by code
   uint32_t* mask = reinterpret_cast<uint32_t*>(area + 2048);   // [8]
@@ -506,13 +523,13 @@ __device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
   const int lane = (int)lane_id();
   const int mtry = x.T->mtry;
   const NodeDesc d = x.sc.big[j];
-  const uint32_t k = rfl(d.k);
+  const uint32_t bt = rfl(x.sc.btask[(size_t)j * mtry + ci]);
   const uint32_t start = rfl(d.start);
   const uint32_t end = start + rfl(d.len);
   const uint32_t N = rfl(d.N);
   const int64_t S = d.S;
-  const int c = (int)rfl(x.sc.cand[(size_t)k * mtry + ci]);
-  const int B = a.n_bins[c];
+  const int c = (int)(bt & 0xFFu);
+  const int B = (int)(bt >> 8);
   for (int b = lane; b < B; b += kWave) L.hv[b] = 0;
   wave_lds_sync();
   // four rows per lane in flight: entries, then codes, then the atomics
@@ -605,7 +622,7 @@ __device__ __forceinline__ void wide_setup(const Ctx& x, const NodeDesc* list, i
   // candidates padded to 8 per node (with the node's last one), read 8 at a time
   const int cst = (mtry + 7) & ~7;
   for (int i = tid; i < nb * cst; i += BLOCK)
-    sh.cand[q][i] = x.sc.cand[(size_t)list[i / cst].k * mtry + min(i % cst, mtry - 1)];
+    sh.cand[q][i] = x.sc.cand[(size_t)list[i / cst].k * cand_stride(mtry) + min(i % cst, mtry - 1)];
 }
 
 // The wide nodes of a level, nb at a time.  Node j of a batch has its rows cut
@@ -821,7 +838,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           continue;
         }
         draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
-                        sc.cand + (size_t)k * mtry);
+                        sc.cand + (size_t)k * cand_stride(mtry));
         work_rows += len;
         ++work_nodes;
         if (len <= kSegMax) {
@@ -835,7 +852,11 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
         } else if (!WIDE || (int32_t)len <= a.huge_min) {
           sc.status[k] = kBig;
-          sc.big[atomicAdd(&sh.cnt[1], 1u)] = NodeDesc{k, st, len, N, S};
+          const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
+          sc.big[j] = NodeDesc{k, st, len, N, S};
+          // each (node, column) task's column and bin count, ready for its wave
+          const uint8_t* ck = sc.cand + (size_t)k * cand_stride(mtry);
+          for (int i = 0; i < mtry; ++i) sc.btask[(size_t)j * mtry + i] = ck[i] | ((uint32_t)a.n_bins[ck[i]] << 8);
         } else {
           sc.status[k] = kHuge;
           sc.huge[atomicAdd(&sh.cnt[2], 1u)] = NodeDesc{k, st, len, N, S};
