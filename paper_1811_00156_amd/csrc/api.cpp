@@ -83,6 +83,7 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   if (const char* e = std::getenv("AIWC_RF_GROW_BLOCK")) cfg.block = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_GROW_WG_PER_CU")) cfg.wg_per_cu = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_HUGE_MIN")) cfg.huge_min = std::atoi(e);
+  if (const char* e = std::getenv("AIWC_RF_GROW_OCC")) cfg.occupancy = std::atoi(e);
   return cfg;
 }
 

@@ -1044,10 +1044,11 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
   (void)wid;
 }
 
-// At most 128 VGPRs (four waves per SIMD): the persistent kernel is bound by
-// latency, so resident waves matter more than the few registers it spills.
-template <int BLOCK, bool WIDE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_grow(GrowArgs a) {
+// OCC waves per SIMD (at most 512 / OCC VGPRs): the persistent kernel is bound
+// by latency, so resident waves can matter more than the registers it spills;
+// the kernel with the wide phase keeps four, the other is built for 4, 5 and 6.
+template <int BLOCK, bool WIDE, int OCC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) void k_grow(GrowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ Shared sh;
   Scratch sc;
@@ -1135,12 +1136,30 @@ Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   return L;
 }
 
-template <int BLOCK, bool WIDE>
-int occupancy(uint32_t lds) {
+// The grow kernel for a launch shape (block, wide phase, waves per SIMD).
+template <int BLOCK>
+const void* grow_kernel(bool wide, int occ) {
+  if (wide) return reinterpret_cast<const void*>(k_grow<BLOCK, true, 4>);
+  switch (occ) {
+    case 5: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 5>);
+    case 6: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 6>);
+    default: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 4>);
+  }
+}
+
+const void* grow_kernel_for(const GrowConfig& cfg, bool wide) {
+  switch (cfg.block) {
+    case 256: return grow_kernel<256>(wide, cfg.occupancy);
+    case 512: return grow_kernel<512>(wide, cfg.occupancy);
+    case 1024: return grow_kernel<1024>(wide, cfg.occupancy);
+    default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
+  }
+}
+
+int occupancy(const void* kernel, int block, uint32_t lds) {
   int nb = 0;
-  AIWC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_grow<BLOCK, WIDE>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grow<BLOCK, WIDE>, BLOCK, lds));
+  AIWC_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  AIWC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, lds));
   return nb;
 }
 
@@ -1172,14 +1191,7 @@ void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C) {
   const uint32_t lds = grow_layout(cfg, mtry_max, C).union_bytes;
   if (lds > device_info().lds_per_block) fail(AIWC_RF_EINVAL, "grow kernel LDS exceeds the device limit");
-  int per_cu = 1;
-  const bool wide = wide_launch(cfg);
-  switch (cfg.block) {
-    case 256: per_cu = wide ? occupancy<256, true>(lds) : occupancy<256, false>(lds); break;
-    case 512: per_cu = wide ? occupancy<512, true>(lds) : occupancy<512, false>(lds); break;
-    case 1024: per_cu = wide ? occupancy<1024, true>(lds) : occupancy<1024, false>(lds); break;
-    default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
-  }
+  int per_cu = occupancy(grow_kernel_for(cfg, wide_launch(cfg)), cfg.block, lds);
   if (per_cu < 1) fail(AIWC_RF_ENOMEM, "grow kernel does not fit the device (LDS or registers)");
   if (cfg.wg_per_cu > 0) per_cu = std::min(per_cu, cfg.wg_per_cu);
   const int64_t slots = (int64_t)device_info().cus * per_cu;
@@ -1217,28 +1229,9 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* cod
   a.union_bytes = L.union_bytes;
   a.wave_bytes = L.wave_bytes;
   a.bstride = L.bstride;
-  const bool wide = wide_launch(cfg);
-  switch (cfg.block) {
-    case 256:
-      if (wide)
-        k_grow<256, true><<<grid, 256, a.union_bytes, s>>>(a);
-      else
-        k_grow<256, false><<<grid, 256, a.union_bytes, s>>>(a);
-      break;
-    case 512:
-      if (wide)
-        k_grow<512, true><<<grid, 512, a.union_bytes, s>>>(a);
-      else
-        k_grow<512, false><<<grid, 512, a.union_bytes, s>>>(a);
-      break;
-    case 1024:
-      if (wide)
-        k_grow<1024, true><<<grid, 1024, a.union_bytes, s>>>(a);
-      else
-        k_grow<1024, false><<<grid, 1024, a.union_bytes, s>>>(a);
-      break;
-    default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
-  }
+  const void* kernel = grow_kernel_for(cfg, wide_launch(cfg));
+  void* args[] = {&a};
+  AIWC_HIP(hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, a.union_bytes, s));
   AIWC_HIP(hipGetLastError());
 }
 

@@ -1,5 +1,6 @@
 // Host runtime of libaiwc_rf: errors, device properties and the device memory
 // cache that every allocation of the library goes through.
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -158,7 +159,7 @@ std::string key_text(const TuneKey& k) {
 struct TuneCache {
   std::mutex mu;
   bool loaded = false;
-  std::map<std::string, std::pair<int, int>> entries;  // key -> (block, huge_min)
+  std::map<std::string, std::array<int, 3>> entries;  // key -> (block, huge_min, occupancy)
 };
 
 TuneCache& tune_cache() {
@@ -175,13 +176,13 @@ void load_file_locked(TuneCache& c) {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    // "<key> | block=<b> huge_min=<h>"
+    // "<key> | block=<b> huge_min=<h> occupancy=<o>"
     char* bar = std::strchr(line, '|');
     if (!bar) continue;
     std::string key(line, bar - line);
     while (!key.empty() && key.back() == ' ') key.pop_back();
-    int b = 0, h = 0;
-    if (std::sscanf(bar + 1, " block=%d huge_min=%d", &b, &h) == 2) c.entries[key] = {b, h};
+    int b = 0, h = 0, o = 0;
+    if (std::sscanf(bar + 1, " block=%d huge_min=%d occupancy=%d", &b, &h, &o) == 3) c.entries[key] = {b, h, o};
   }
   std::fclose(f);
 }
@@ -194,8 +195,9 @@ bool tune_lookup(const TuneKey& key, GrowConfig* cfg) {
   load_file_locked(c);
   auto it = c.entries.find(key_text(key));
   if (it == c.entries.end()) return false;
-  cfg->block = it->second.first;
-  cfg->huge_min = it->second.second;
+  cfg->block = it->second[0];
+  cfg->huge_min = it->second[1];
+  cfg->occupancy = it->second[2];
   return true;
 }
 
@@ -204,10 +206,10 @@ void tune_store(const TuneKey& key, const GrowConfig& cfg) {
   std::lock_guard<std::mutex> g(c.mu);
   load_file_locked(c);
   const std::string k = key_text(key);
-  c.entries[k] = {cfg.block, cfg.huge_min};
+  c.entries[k] = {cfg.block, cfg.huge_min, cfg.occupancy};
   if (const char* path = std::getenv("AIWC_RF_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s | block=%d huge_min=%d\n", k.c_str(), cfg.block, cfg.huge_min);
+      std::fprintf(f, "%s | block=%d huge_min=%d occupancy=%d\n", k.c_str(), cfg.block, cfg.huge_min, cfg.occupancy);
       std::fclose(f);
     }
   }
@@ -215,7 +217,8 @@ void tune_store(const TuneKey& key, const GrowConfig& cfg) {
 
 std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
   // workgroup size x wide-node limit; a limit at or above the largest training
-  // set means no wide nodes, which is timed once per workgroup size
+  // set means no wide nodes, timed once per workgroup size at 4, 5 and 6 waves
+  // per SIMD
   std::vector<GrowConfig> out;
   for (int block : {256, 512, 1024}) {
     bool narrow_done = false;
@@ -223,10 +226,14 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
       const bool narrow = base.n_cap <= h;
       if (narrow && narrow_done) continue;
       narrow_done = narrow_done || narrow;
-      GrowConfig c = base;
-      c.block = block;
-      c.huge_min = h;
-      out.push_back(c);
+      for (int occ : {4, 5, 6}) {
+        if (!narrow && occ != 4) continue;
+        GrowConfig c = base;
+        c.block = block;
+        c.huge_min = h;
+        c.occupancy = occ;
+        out.push_back(c);
+      }
     }
   }
   return out;

@@ -122,3 +122,15 @@ def test_wide_code_rows_and_many_candidates(block, huge_min):
                 os.environ[k] = v
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"wide rows block {block} huge_min {huge_min} tree {t}")
+
+
+@pytest.mark.parametrize("block", ["256", "512", "1024"])
+@pytest.mark.parametrize("occ", ["5", "6"])
+def test_occupancy_variants(setup, block, occ):
+    """The kernel without the wide phase built for 5 and 6 waves per SIMD grows
+    the same trees."""
+    rf, ds, ob, of = setup
+    log(f"occupancy block={block} occ={occ}")
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": "100000", "AIWC_RF_GROW_OCC": occ})
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"block {block} occupancy {occ} tree {t}")
