@@ -151,14 +151,20 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
       continue;  // the shape does not fit this device
     }
     DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
-    launch_init(nullptr, queue, s);
-    AIWC_HIP(hipEventRecord(e0, s));
-    launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial, F->nodes.p,
-                F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p, base.n_cap, mtry_max, grid, s);
-    AIWC_HIP(hipEventRecord(e1, s));
-    AIWC_HIP(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    AIWC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    // each shape is timed twice and keeps its faster run
+    float ms = -1.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      launch_init(nullptr, queue, s);
+      AIWC_HIP(hipEventRecord(e0, s));
+      launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial,
+                  F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p,
+                  base.n_cap, mtry_max, grid, s);
+      AIWC_HIP(hipEventRecord(e1, s));
+      AIWC_HIP(hipEventSynchronize(e1));
+      float m = 0.0f;
+      AIWC_HIP(hipEventElapsedTime(&m, e0, e1));
+      if (ms < 0.0f || m < ms) ms = m;
+    }
     if (best_ms < 0.0f || ms < best_ms) {
       best_ms = ms;
       best = c;
