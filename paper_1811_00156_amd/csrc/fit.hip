@@ -777,26 +777,39 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     }
     __syncthreads();
   }
-  // in-bag entries, ascending local row order; root sums
+  // in-bag entries and root sums; each thread takes eight rows per pass,
+  // strided by the block, so a pass costs one workgroup scan (the order of the
+  // entries is free: every later sum over them is exact)
   uint32_t n_inbag = 0;
   uint64_t N0 = 0, Q0 = 0;
   int64_t S0 = 0;
-  for (int64_t base = 0; base < n; base += BLOCK) {
-    const int64_t i = base + tid;
-    const uint32_t c = i < n ? sc.cnt[i] : 0u;
-    // in-bag bitmap: this wave's 64 consecutive rows form one word
-    const uint64_t bits = __ballot(c > 0);
-    const int64_t wbase = base + (int64_t)(tid / kWave) * kWave;
-    if (lane_id() == 0 && T.inbag_off >= 0 && wbase < n) a.inbag[T.inbag_off + wbase / kWave] = bits;
+  constexpr int R = 8;
+  for (int64_t base = 0; base < n; base += (int64_t)R * BLOCK) {
+    uint32_t c[R];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + (int64_t)r * BLOCK + tid;
+      c[r] = i < n ? sc.cnt[i] : 0u;
+      mine += c[r] > 0 ? 1u : 0u;
+      // in-bag bitmap: this wave's 64 consecutive rows form one word
+      const uint64_t bits = __ballot(c[r] > 0);
+      const int64_t wbase = base + (int64_t)r * BLOCK + (int64_t)(tid / kWave) * kWave;
+      if (lane_id() == 0 && T.inbag_off >= 0 && wbase < n) a.inbag[T.inbag_off + wbase / kWave] = bits;
+    }
     uint32_t total;
-    const uint32_t pos = block_exscan<BLOCK>(c > 0 ? 1u : 0u, sh.tmp, total) + n_inbag;
-    if (c > 0) {
-      const uint32_t row = train ? (uint32_t)train[i] : (uint32_t)i;
-      const int64_t y = a.y_fp[row];
-      sc.L0.buf[pos] = entry_pack(row, c, y);
-      N0 += c;
-      S0 += (int64_t)c * y;
-      Q0 += (uint64_t)((int64_t)c * y * y);
+    uint32_t pos = block_exscan<BLOCK>(mine, sh.tmp, total) + n_inbag;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (c[r] > 0) {
+        const int64_t i = base + (int64_t)r * BLOCK + tid;
+        const uint32_t row = train ? (uint32_t)train[i] : (uint32_t)i;
+        const int64_t y = a.y_fp[row];
+        sc.L0.buf[pos++] = entry_pack(row, c[r], y);
+        N0 += c[r];
+        S0 += (int64_t)c[r] * y;
+        Q0 += (uint64_t)((int64_t)c[r] * y * y);
+      }
     }
     n_inbag += total;
   }
