@@ -101,26 +101,43 @@ def measured_traffic(kernel_key):
     return rec["traffic_bytes"]
 
 
-def run_cpu_baseline(wl, ds, sample_trees, steps_cap_s=30.0):
+CPU_TARGET_S = 12.0  # seconds of oracle work per CPU baseline
+
+
+def run_cpu_baseline(wl, ds, probe_trees):
+    """The oracle's whole-step throughput on the host: bin once, then fit and
+    predict trees of the same forest (repeating the whole forest when it takes
+    less) until about CPU_TARGET_S seconds of work; a first pass of probe_trees
+    trees sizes the sample."""
     from oracle import oracle as O
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     b = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
     t_bin = time.perf_counter() - t0
+    nt = wl["num_trees"]
+
+    def fit_predict(k):
+        f = O.fit(b.codes, b.n_bins, ds.y, nt, wl["mtry"], wl["min_node"], seed=1, trees=range(k), n_threads=cores)
+        O.predict(f, b.codes)
+
+    probe = min(probe_trees, nt)
     t0 = time.perf_counter()
-    f = O.fit(b.codes, b.n_bins, ds.y, wl["num_trees"], wl["mtry"], wl["min_node"], seed=1,
-              trees=range(sample_trees), n_threads=cores)
-    t_fit = time.perf_counter() - t0
+    fit_predict(probe)
+    per_tree = (time.perf_counter() - t0) / probe
+    want = max(probe, int(CPU_TARGET_S / max(per_tree, 1e-9)))
     t0 = time.perf_counter()
-    O.predict(f, b.codes)
-    t_pred = time.perf_counter() - t0
-    # scale the sampled trees to the whole forest: fit and predict are linear in trees
-    scale = wl["num_trees"] / sample_trees
-    step_s = t_bin + (t_fit + t_pred) * scale
-    return {"value": ds.n * wl["num_trees"] / step_s, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
-            "sample": f"bin all {ds.n} rows + fit and predict {sample_trees} of {wl['num_trees']} trees "
-                      f"(scaled x{scale:g}); measured {t_bin + t_fit + t_pred:.1f} s"}
+    done = 0
+    while done < want:
+        k = min(nt, want - done)
+        fit_predict(k)
+        done += k
+    el = time.perf_counter() - t0
+    # one step = bin + fit and predict the whole forest; fit and predict are linear in trees
+    step_s = t_bin + el * nt / done
+    return {"value": ds.n * nt / step_s, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+            "sample": f"bin all {ds.n} rows ({t_bin:.2f} s) + fit and predict {done} trees of the {nt}-tree forest "
+                      f"({el:.1f} s), scaled to one step"}
 
 
 def bench_forest(args, wl_name):
@@ -202,7 +219,7 @@ def bench_forest(args, wl_name):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        sample = {"c1": 100, "c2": 2000, "c3": 16}.get(wl_name, 16)
+        sample = {"c1": 100, "c2": 200, "c3": 16}.get(wl_name, 16)
         res["cpu_baseline"] = run_cpu_baseline(wl, ds, sample)
     forests.clear()
     return res
@@ -277,18 +294,22 @@ def bench_grid(args):
 
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         ob = O.bin(ds.X, ds.device, ds.n_devices, 64)
+        # random forests of the grid, whole, until about CPU_TARGET_S seconds of work
         rng = np.random.default_rng(0)
-        pick = rng.choice(len(combos), size=6, replace=False)
+        pick = rng.permutation(len(combos))
         t0 = time.perf_counter()
-        rt = 0
+        rt = used = 0
         for k in pick:
             f, m, mn = combos[k]
             train = np.nonzero(folds != f)[0]
             O.fit(ob.codes, ob.n_bins, ds.y, 256, m, mn, seed=1, train_rows=train, n_threads=cores)
             rt += train.shape[0] * 256
+            used += 1
+            if time.perf_counter() - t0 >= CPU_TARGET_S:
+                break
         el = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
-                               "sample": f"6 random forests of the grid (256 trees each), {el:.1f} s"}
+                               "sample": f"{used} random forests of the grid (256 trees each), {el:.1f} s"}
     return res
 
 
