@@ -126,13 +126,17 @@ def run_cpu_baseline(wl, ds, probe_trees):
     fit_predict(probe)
     per_tree = (time.perf_counter() - t0) / probe
     want = max(probe, int(CPU_TARGET_S / max(per_tree, 1e-9)))
+    # in pieces of about an eighth of the estimate, stopping once the target
+    # time is spent (the probe can misjudge the host's sustained rate)
+    piece = max(probe, want // 8)
     t0 = time.perf_counter()
     done = 0
-    while done < want:
-        k = min(nt, want - done)
+    el = 0.0
+    while done < want and (done == 0 or el < CPU_TARGET_S):
+        k = min(nt, want - done, piece)
         fit_predict(k)
         done += k
-    el = time.perf_counter() - t0
+        el = time.perf_counter() - t0
     # one step = bin + fit and predict the whole forest; fit and predict are linear in trees
     step_s = t_bin + el * nt / done
     return {"value": ds.n * nt / step_s, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",

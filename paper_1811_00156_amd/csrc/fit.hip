@@ -597,6 +597,7 @@ struct Shared {
   uint64_t red[16];
   uint32_t cnt[3 + kSegClasses];  // [1] large, [2] wide, [3..] small nodes per segment width
   uint32_t task;
+  uint32_t next_task;  // the split-search tasks' queue head
   // two wide batches (the one being searched and the next): node j's first
   // entry, rows, first chunk, weight, sum, and its candidates at
   // j * round_up(mtry, 8) + i
@@ -838,6 +839,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
     const Ctx x{&a, &T, sc, C.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
     // (a) leaf rules, candidate draws, tiers
     if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
+    if (tid == 0) sh.next_task = NW;
     __syncthreads();
     if (tid < n_draw) {
       for (uint32_t k = tid; k < level_cnt; k += n_draw) {
@@ -889,7 +891,9 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         hc = max(8, (int)a.union_bytes / (a.bstride * 8) / 8 * 8);
       wide_phase<BLOCK>(x, sc.huge, n_huge, nb, hc, n_big, lds, sh);
     }
-    // (c) large-node columns and small-node segments, one wave each
+    // (c) large-node columns and small-node segments, one wave each; a wave
+    // takes its next task from the queue head when it starts one (their costs
+    // differ widely, so a fixed deal would leave waves idle at the barrier)
     {
       const uint32_t n_big_tasks = n_big * (uint32_t)mtry;
       uint32_t first[kSegClasses + 1];
@@ -899,7 +903,9 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
         first[c + 1] = first[c] + (sh.cnt[3 + c] + per_wave - 1) / per_wave;
       }
       WaveHist& wl = *reinterpret_cast<WaveHist*>(lds + (size_t)wid * a.wave_bytes);
-      for (uint32_t t = wid; t < first[kSegClasses]; t += NW) {
+      for (uint32_t t = wid; t < first[kSegClasses];) {
+        uint32_t t_next = 0;
+        if (lane == 0) t_next = atomicAdd(&sh.next_task, 1u);
         if (t < n_big_tasks)
           big_task(x, t / mtry, (int)(t % mtry), wl);
         else if (t < first[1])
@@ -912,6 +918,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           small_task<32>(x, sc.seg[3], t - first[3], sh.cnt[6], wl);
         else
           rank_task(x, sc.seg[4], t - first[4], sh.cnt[7], wl);
+        t = read_lane(t_next, 0);
       }
     }
     __syncthreads();
