@@ -255,9 +255,13 @@ def bench_grid(args):
         torch.cuda.synchronize()
         return g, (time.perf_counter() - t0) * 1000.0
 
+    # the warmup runs both paths, so that each one's launch shapes are tuned
+    # before the timed steps
     for i in range(args.warmup):
         log(f"grid warmup {i}")
         g, _ = run(rf.FIT_FUSED | tune_flag())
+        del g
+        g, _ = run(rf.FIT_PLAIN | tune_flag())
         del g
     fused_ms, plain_ms, grow_ms = [], [], []
     for i in range(args.steps):

@@ -70,12 +70,16 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   GrowConfig cfg;
   // large training sets: 512 threads per tree, every node above 64 rows in
   // workgroup-wide batches; small ones: 512 threads per tree while trees are
-  // few, 256 once there are enough trees to fill four workgroups per CU
+  // few, and once there are enough trees to fill several workgroups per CU,
+  // 192 threads at 6 waves per SIMD (eight resident trees per CU)
   if (n_cap > 16384) {
     cfg.block = 512;
     cfg.huge_min = 64;
+  } else if (n_tasks >= 4LL * device_info().cus) {
+    cfg.block = 192;
+    cfg.occupancy = 6;
   } else {
-    cfg.block = n_tasks >= 4LL * device_info().cus ? 256 : 512;
+    cfg.block = 512;
   }
   cfg.n_cap = n_cap;
   cfg.bins_max = 1;

@@ -1169,6 +1169,7 @@ const void* grow_kernel(bool wide, int occ) {
 
 const void* grow_kernel_for(const GrowConfig& cfg, bool wide) {
   switch (cfg.block) {
+    case 192: return grow_kernel<192>(wide, cfg.occupancy);
     case 256: return grow_kernel<256>(wide, cfg.occupancy);
     case 512: return grow_kernel<512>(wide, cfg.occupancy);
     case 1024: return grow_kernel<1024>(wide, cfg.occupancy);

@@ -220,7 +220,7 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
   // set means no wide nodes, timed once per workgroup size at 4, 5 and 6 waves
   // per SIMD
   std::vector<GrowConfig> out;
-  for (int block : {256, 512, 1024}) {
+  for (int block : {192, 256, 512, 1024}) {
     bool narrow_done = false;
     for (int h : {64, 512, 4096}) {
       const bool narrow = base.n_cap <= h;

@@ -40,7 +40,7 @@ def fit_with(rf, ds, ob, env, flags=0):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("block", ["256", "512", "1024"])
+@pytest.mark.parametrize("block", ["192", "256", "512", "1024"])
 @pytest.mark.parametrize("huge_min", ["64", "300", "2048", "4096", "100000"])
 def test_shape_invariance(setup, block, huge_min):
     rf, ds, ob, of = setup
@@ -62,7 +62,7 @@ def test_autotuned_fit_matches(setup):
     assert np.array_equal(rf.aiwc_rf_predict(f, codes).cpu().numpy().view(np.uint64), yhat.view(np.uint64))
 
 
-@pytest.mark.parametrize("block", ["256", "1024"])
+@pytest.mark.parametrize("block", ["192", "256", "1024"])
 def test_wide_batches_in_column_chunks(block):
     """Every node above 64 rows in workgroup-wide batches, with more candidate
     columns (35 of 35, 256 bins) than one batch's LDS holds at a 256-thread
@@ -124,7 +124,7 @@ def test_wide_code_rows_and_many_candidates(block, huge_min):
         assert_tree_equal(tree, of.tree(t), f"wide rows block {block} huge_min {huge_min} tree {t}")
 
 
-@pytest.mark.parametrize("block", ["256", "512", "1024"])
+@pytest.mark.parametrize("block", ["192", "256", "512", "1024"])
 @pytest.mark.parametrize("occ", ["5", "6"])
 def test_occupancy_variants(setup, block, occ):
     """The kernel without the wide phase built for 5 and 6 waves per SIMD grows
