@@ -76,6 +76,14 @@ struct Level2 {
 // repeats the last candidate), so that it can be read with 16-byte loads.
 __host__ __device__ inline int cand_stride(int mtry) { return (mtry + 15) & ~15; }
 
+// A split node's partition state, by its rank among the level's split nodes:
+// the next free slots from the left and from the right of its entry range, and
+// the left side's sum of w y^2.
+struct Cursor {
+  uint32_t L, R;
+  uint64_t q;
+};
+
 struct Scratch {
   uint32_t* cnt;
   Level2 L0, L1;
@@ -86,11 +94,8 @@ struct Scratch {
   uint8_t* dbin;
   uint32_t* dNL;
   int64_t* dSL;
-  uint64_t* qacc;  // split node k's left-side sum of w y^2, added up by the partition
-  uint32_t* rank;
-  uint32_t* curL;
-  uint32_t* curR;
-  uint2* chunks;  // partition work: (split node, first entry) of every 64-entry chunk
+  Cursor* cur;    // by split rank, when a level's do not fit the LDS
+  uint4* chunks;  // partition work per 64-entry chunk: first entry, the node's end, split rank, column | bin << 8
   NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
   NodeDesc* big;
   NodeDesc* huge;
@@ -123,13 +128,10 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->dbin = reinterpret_cast<uint8_t*>(take(n));
   s->dNL = reinterpret_cast<uint32_t*>(take(4 * n));
   s->dSL = reinterpret_cast<int64_t*>(take(8 * n));
-  s->qacc = reinterpret_cast<uint64_t*>(take(8 * n));
-  s->rank = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->curL = reinterpret_cast<uint32_t*>(take(4 * n));
-  s->curR = reinterpret_cast<uint32_t*>(take(4 * n));
   // a split node holds at least two rows, so a level has at most n/2 of them
   // and at most n/64 + n/2 chunks
-  s->chunks = reinterpret_cast<uint2*>(take(sizeof(uint2) * (n / 64 + n / 2 + 2)));
+  s->cur = reinterpret_cast<Cursor*>(take(sizeof(Cursor) * (n / 2 + 1)));
+  s->chunks = reinterpret_cast<uint4*>(take(sizeof(uint4) * (n / 64 + n / 2 + 2)));
   // class c holds nodes of more than 2 << c rows (c >= 1)
   for (int c = 0; c < kSegClasses; ++c)
     s->seg[c] = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * (n / (1 + (c ? (2u << c) : 0)) + 1)));
@@ -753,11 +755,64 @@ __device__ void wide_phase(const Ctx& x, const NodeDesc* list, uint32_t n_wide, 
   }
 }
 
+// One wave per chunk of 64 entries of a split node: the lanes that go left take
+// consecutive slots from the left cursor in lane order, the others from the
+// right cursor, one atomic each; the left side's sum of w y^2 is added up on
+// the way.  Rows of leaves are not touched again.  Four chunks per wave are in
+// flight at a time, so that their dependent loads (chunk, entry, code)
+// overlap.  `cur` is in LDS or in global memory (inlined once for each).
+template <int BLOCK>
+__device__ __forceinline__ void partition_level(const Ctx& x, uint64_t* __restrict__ out, Cursor* cur,
+                                                uint32_t n_chunks) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int UP = 4;
+  const GrowArgs& a = *x.a;
+  const int lane = (int)lane_id();
+  for (uint32_t c0 = threadIdx.x / kWave; c0 < n_chunks; c0 += UP * NW) {
+    uint32_t rk[UP], col[UP], bin[UP];
+    uint64_t e[UP];
+    bool mv[UP], go_left[UP];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      const uint32_t ch = c0 + (uint32_t)(u * NW);
+      const uint4 cw = ch < n_chunks ? x.sc.chunks[ch] : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t p0 = rfl(cw.x), en = rfl(cw.y), cb = rfl(cw.w);
+      rk[u] = rfl(cw.z);
+      col[u] = cb & 0xFFu;
+      bin[u] = cb >> 8;
+      const uint32_t p = p0 + (uint32_t)lane;
+      mv[u] = p < en;
+      e[u] = mv[u] ? x.buf[p] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < UP; ++u)
+      go_left[u] = mv[u] && a.codes[(size_t)entry_row(e[u]) * a.C + col[u]] <= bin[u];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      if (c0 + (uint32_t)(u * NW) >= n_chunks) break;
+      const uint64_t lm = __ballot(go_left[u]), rm = __ballot(mv[u] && !go_left[u]);
+      const uint64_t below = (1ull << lane) - 1ull;
+      uint32_t bl = 0, br = 0;
+      if (lane == 0) {
+        const uint32_t nl = (uint32_t)__popcll(lm), nr = (uint32_t)__popcll(rm);
+        if (nl) bl = atomicAdd(&cur[rk[u]].L, nl);
+        if (nr) br = atomicSub(&cur[rk[u]].R, nr) - nr;
+      }
+      bl = read_lane(bl, 0);
+      br = read_lane(br, 0);
+      if (mv[u]) out[go_left[u] ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e[u];
+      const int64_t y = entry_y(e[u]);
+      const uint64_t q = wave_sum(go_left[u] ? (uint64_t)((int64_t)entry_w(e[u]) * y * y) : 0ull);
+      if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&cur[rk[u]].q, (unsigned long long)q);
+    }
+  }
+}
+
 // WIDE: the launch may hold nodes above the wide limit (the kernel without
 // the wide-batch phase is compiled separately, so that small training sets
 // keep its leaner register allocation).
 template <int BLOCK, bool WIDE>
-__device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, uint8_t* lds,
+__device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, uint8_t* lds,
                           Shared& sh) {
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
@@ -927,7 +982,11 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       decide_from_recs(x, j < n_big ? sc.big[j].k : sc.huge[j - n_big].k, sc.recs + (size_t)j * mtry, mtry);
     __syncthreads();
     // (e) breadth-first child ids, node words, children's sums and cursors, and
-    // the partition's chunks of 64 entries of every split node
+    // the partition's chunks of 64 entries of every split node.  The cursors
+    // live in the LDS union area (free until the next level) when the level's
+    // nodes fit it, else in scratch.
+    const bool lds_cur = level_cnt <= a.union_bytes / (uint32_t)sizeof(Cursor);
+    Cursor* lcur = reinterpret_cast<Cursor*>(lds);
     uint32_t n_split = 0, n_chunks = 0;
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
       const uint32_t k = b0 + tid;
@@ -939,8 +998,10 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       const uint32_t cfirst = block_exscan<BLOCK>(nch, sh.tmp, ctotal) + n_chunks;
       // (the bounds below hold by construction; the guards keep a broken
       // invariant from writing outside the scratch arrays)
-      if ((uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2))
-        for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint2(k, x.mstart[k] + c * kWave);
+      if (nch > 0 && (uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2)) {
+        const uint32_t st = x.mstart[k], en = x.mend[k], cb = (uint32_t)sc.dcol[k] | ((uint32_t)sc.dbin[k] << 8);
+        for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint4(st + c * kWave, en, r, cb);
+      }
       if (in) {
         const uint32_t node = level_lo + k;
         const uint32_t N = x.mN[k];
@@ -954,12 +1015,13 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           } else {
             atomicOr(a.status, kStatusCapacity);
           }
-          sc.rank[k] = r;
           const uint32_t st = x.mstart[k], en = x.mend[k];
           work_part += en - st;
-          sc.curL[k] = st;
-          sc.curR[k] = en;
-          sc.qacc[k] = 0;
+          const Cursor c0{st, en, 0ull};
+          if (lds_cur)
+            lcur[r] = c0;
+          else
+            sc.cur[r] = c0;
           const uint32_t NL = sc.dNL[k];
           const int64_t SL = sc.dSL[k];
           X.mstart[2 * r] = st;
@@ -968,6 +1030,7 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
           X.mend[2 * r + 1] = en;
           X.mN[2 * r + 1] = N - NL;
           X.mS[2 * r + 1] = S - SL;
+          X.mQ[2 * r + 1] = x.mQ[k];  // the parent's, until the left side's is known
         } else {
           a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
         }
@@ -984,65 +1047,19 @@ __device__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_ind
       next_id = (uint32_t)T.capacity;
       break;
     }
-    // (f) partition the entries of split nodes into their children's segments,
-    // one wave per chunk of 64 entries of one node: the lanes that go left take
-    // consecutive slots from the left cursor in lane order, the others from
-    // the right cursor, one atomic each; the left side's sum of w y^2 is added
-    // up on the way.  Rows of leaves are not touched again.
-    // Four chunks per wave are in flight at a time, so that their dependent
-    // loads (chunk, node, entry, code) overlap.
-    constexpr int UP = 4;
-    for (uint32_t c0 = (uint32_t)wid; c0 < n_chunks; c0 += UP * NW) {
-      uint32_t k[UP], en[UP], col[UP], bin[UP];
-      uint64_t e[UP];
-      bool mv[UP], go_left[UP];
-#pragma unroll
-      for (int u = 0; u < UP; ++u) {
-        const uint32_t ch = c0 + (uint32_t)(u * NW);
-        const uint2 cw = ch < n_chunks ? sc.chunks[ch] : make_uint2(0u, 0xFFFFFFFFu);
-        k[u] = rfl(cw.x);
-        const uint32_t p0 = rfl(cw.y);
-        en[u] = ch < n_chunks ? x.mend[k[u]] : 0u;
-        col[u] = sc.dcol[k[u]];
-        bin[u] = sc.dbin[k[u]];
-        const uint32_t p = p0 + (uint32_t)lane;
-        mv[u] = ch < n_chunks && p < en[u];
-        e[u] = mv[u] ? C.buf[p] : 0ull;
-      }
-#pragma unroll
-      for (int u = 0; u < UP; ++u)
-        go_left[u] = mv[u] && a.codes[(size_t)entry_row(e[u]) * a.C + col[u]] <= bin[u];
-#pragma unroll
-      for (int u = 0; u < UP; ++u) {
-        if (c0 + (uint32_t)(u * NW) >= n_chunks) break;
-        const uint64_t lm = __ballot(go_left[u]), rm = __ballot(mv[u] && !go_left[u]);
-        const uint64_t below = (1ull << lane) - 1ull;
-        uint32_t bl = 0, br = 0;
-        if (lane == 0) {
-          const uint32_t nl = (uint32_t)__popcll(lm), nr = (uint32_t)__popcll(rm);
-          if (nl) bl = atomicAdd(&sc.curL[k[u]], nl);
-          if (nr) br = atomicSub(&sc.curR[k[u]], nr) - nr;
-        }
-        bl = read_lane(bl, 0);
-        br = read_lane(br, 0);
-        if (mv[u])
-          X.buf[go_left[u] ? bl + (uint32_t)__popcll(lm & below) : br + (uint32_t)__popcll(rm & below)] = e[u];
-        const int64_t y = entry_y(e[u]);
-        const uint64_t q = wave_sum(go_left[u] ? (uint64_t)((int64_t)entry_w(e[u]) * y * y) : 0ull);
-        if (lane == 0 && q != 0) atomicAdd((unsigned long long*)&sc.qacc[k[u]], (unsigned long long)q);
-      }
-    }
+    // (f) partition the entries of split nodes into their children's segments
+    if (lds_cur)
+      partition_level<BLOCK>(x, X.buf, lcur, n_chunks);
+    else
+      partition_level<BLOCK>(x, X.buf, sc.cur, n_chunks);
     __syncthreads();
     // (g) the boundary between each pair of children, and their sums of w y^2
-    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-      if (sc.status[k] == kSplit) {
-        const uint32_t r = sc.rank[k];
-        const uint64_t QL = sc.qacc[k];
-        X.mend[2 * r] = sc.curL[k];
-        X.mstart[2 * r + 1] = sc.curL[k];
-        X.mQ[2 * r] = QL;
-        X.mQ[2 * r + 1] = x.mQ[k] - QL;
-      }
+    for (uint32_t r = tid; r < n_split; r += BLOCK) {
+      const Cursor c = lds_cur ? lcur[r] : sc.cur[r];
+      X.mend[2 * r] = c.L;
+      X.mstart[2 * r + 1] = c.L;
+      X.mQ[2 * r] = c.q;
+      X.mQ[2 * r + 1] -= c.q;
     }
     __syncthreads();
     level_lo = next_id;
