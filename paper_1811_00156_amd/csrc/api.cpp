@@ -71,13 +71,17 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   // large training sets: 512 threads per tree, every node above 64 rows in
   // workgroup-wide batches; small ones: 512 threads per tree while trees are
   // few, and once there are enough trees to fill several workgroups per CU,
-  // 192 threads at 6 waves per SIMD (eight resident trees per CU)
+  // 192 threads at 6 waves per SIMD (eight resident trees per CU).  A
+  // large-node task takes one candidate column while trees are few (more
+  // waves per tree), up to four once the CUs are full.
+  cfg.big_cols = 1;
   if (n_cap > 16384) {
     cfg.block = 512;
     cfg.huge_min = 64;
   } else if (n_tasks >= 4LL * device_info().cus) {
     cfg.block = 192;
     cfg.occupancy = 6;
+    cfg.big_cols = 4;
   } else {
     cfg.block = 512;
   }
@@ -88,6 +92,7 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   if (const char* e = std::getenv("AIWC_RF_GROW_WG_PER_CU")) cfg.wg_per_cu = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_HUGE_MIN")) cfg.huge_min = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_GROW_OCC")) cfg.occupancy = std::atoi(e);
+  if (const char* e = std::getenv("AIWC_RF_BIG_COLS")) cfg.big_cols = std::atoi(e);
   return cfg;
 }
 

@@ -172,6 +172,8 @@ struct GrowArgs {
   int32_t mtry_max;
   int32_t huge_min;  // nodes with more rows than this are searched in workgroup-wide batches
   int32_t bstride;   // bins per column histogram in the workgroup-wide layout
+  int32_t big_cols;    // candidate columns per large-node task (1 .. 4)
+  int32_t big_stride;  // bins per column histogram of a large-node task
   size_t scratch_stride;
   uint32_t union_bytes;  // dynamic LDS
   uint32_t wave_bytes;   // per-wave area of the split-search tasks
@@ -219,7 +221,7 @@ __device__ __forceinline__ T block_sum(T v, T* tmp) {
 // k + floor(r_k (C-k) / 2^64).  `perm` is this thread's C-entry LDS row
 // (stride `pst` bytes between entries).  The chosen columns are written
 // ascending to `out`.
-__device__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t node, uint32_t tree, int C, int mtry,
+__device__ __forceinline__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t node, uint32_t tree, int C, int mtry,
                                 uint8_t* out) {
   for (int c = 0; c < C; ++c) perm[c * pst] = (uint8_t)c;
   uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
@@ -303,7 +305,7 @@ __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node
 }
 
 template <int W>
-__device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
+__device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
   const int lane = (int)lane_id();
@@ -384,7 +386,7 @@ __device__ void small_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint3
 // occur, the occurring codes are ranked through a 256-bit presence mask, and a
 // wave prefix scan over the ranked codes gives the left sums of every split
 // (cost independent of the bin count and of the number of rows).
-__device__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
+__device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
   const int lane = (int)lane_id();
@@ -519,56 +521,75 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
   return wave_argmax(lbest, lbin);
 }
 
-// Large nodes: one wave per (node, candidate column) with an LDS histogram.
-__device__ void big_task(const Ctx& x, uint32_t j, int ci, WaveHist& L) {
+// Large nodes: one wave per (node, up to four consecutive candidate columns),
+// one LDS histogram per column: the node's entries are read once for all of
+// them and the columns' code gathers overlap.
+__device__ __forceinline__ void big_task(const Ctx& x, uint32_t j, int ci0, WaveHist& L) {
+  constexpr int G = 4;
   const GrowArgs& a = *x.a;
   const int lane = (int)lane_id();
   const int mtry = x.T->mtry;
+  const int gn = min(a.big_cols, mtry - ci0);  // columns of this task
+  const int gs = a.big_stride;
   const NodeDesc d = x.sc.big[j];
-  const uint32_t bt = rfl(x.sc.btask[(size_t)j * mtry + ci]);
   const uint32_t start = rfl(d.start);
   const uint32_t end = start + rfl(d.len);
   const uint32_t N = rfl(d.N);
   const int64_t S = d.S;
-  const int c = (int)(bt & 0xFFu);
-  const int B = (int)(bt >> 8);
-  for (int b = lane; b < B; b += kWave) L.hv[b] = 0;
+  const uint32_t* bt = x.sc.btask + (size_t)j * mtry + ci0;
+  int c[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) c[g] = g < gn ? (int)(rfl(bt[g]) & 0xFFu) : 0;
+  uint64_t* hv = L.hv;
+  for (int b = lane; b < gn * gs; b += kWave) hv[b] = 0;
   wave_lds_sync();
-  // four rows per lane in flight: entries, then codes, then the atomics
-  constexpr int U = 4;
+  // two rows per lane in flight: entries, then their codes in every column,
+  // then the atomics
+  constexpr int U = 2;
   for (uint32_t p0 = start + lane; p0 < end; p0 += U * kWave) {
     uint64_t e[U];
-    uint32_t code[U];
+    uint32_t code[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) e[u] = p0 + u * kWave < end ? x.buf[p0 + u * kWave] : 0ull;
 #pragma unroll
-    for (int u = 0; u < U; ++u) code[u] = p0 + u * kWave < end ? a.codes[(size_t)entry_row(e[u]) * a.C + c] : 0u;
+    for (int u = 0; u < U; ++u) {
+      const uint8_t* rp = a.codes + (size_t)entry_row(e[u]) * a.C;
+#pragma unroll
+      for (int g = 0; g < G; ++g) code[u][g] = (g < gn && p0 + u * kWave < end) ? rp[c[g]] : 0u;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (p0 + u * kWave < end) {
         const uint32_t w = entry_w(e[u]);
-        atomicAdd((unsigned long long*)&L.hv[code[u]], (unsigned long long)pack_ns(w, (int64_t)w * entry_y(e[u])));
+        const uint64_t v = pack_ns(w, (int64_t)w * entry_y(e[u]));
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (g < gn) atomicAdd((unsigned long long*)&hv[g * gs + (int)code[u][g]], (unsigned long long)v);
       }
     }
   }
   wave_lds_sync();
-  uint32_t NL;
-  int64_t SL;
-  const ArgMax am = scan_packed(L.hv, B, N, S, NL, SL);
-  if (lane == am.lane) {
-    Rec r;
-    r.score = am.score;
-    r.SL = SL;
-    r.NL = NL;
-    r.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
-    x.sc.recs[(size_t)j * mtry + ci] = r;
+#pragma unroll 1
+  for (int g = 0; g < gn; ++g) {
+    const uint32_t t = rfl(bt[g]);
+    uint32_t NL;
+    int64_t SL;
+    const ArgMax am = scan_packed(hv + g * gs, (int)(t >> 8), N, S, NL, SL);
+    if (lane == am.lane) {
+      Rec r;
+      r.score = am.score;
+      r.SL = SL;
+      r.NL = NL;
+      r.colbin = ((t & 0xFFu) << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
+      x.sc.recs[(size_t)j * mtry + ci0 + g] = r;
+    }
   }
   wave_lds_sync();
 }
 
 // Decide a node from its per-column records (columns ascending: keep the
 // first strictly greater score).
-__device__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int mtry) {
+__device__ __forceinline__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int mtry) {
   double best = -1.0;
   int bi = -1;
   for (int i = 0; i < mtry; ++i) {
@@ -638,7 +659,7 @@ __device__ __forceinline__ void wide_setup(const Ctx& x, const NodeDesc* list, i
 // column's record (decided with the other nodes' after the phase) and zeroes
 // the bins it read, while the next batch's metadata is staged.
 template <int BLOCK>
-__device__ void wide_phase(const Ctx& x, const NodeDesc* list, uint32_t n_wide, int nb_max, int hc, uint32_t rec_base,
+__device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, uint32_t n_wide, int nb_max, int hc, uint32_t rec_base,
                            uint8_t* lds, Shared& sh) {
   constexpr int NW = BLOCK / kWave;
   const GrowArgs& a = *x.a;
@@ -950,7 +971,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     // takes its next task from the queue head when it starts one (their costs
     // differ widely, so a fixed deal would leave waves idle at the barrier)
     {
-      const uint32_t n_big_tasks = n_big * (uint32_t)mtry;
+      const uint32_t per_big = (uint32_t)((mtry + a.big_cols - 1) / a.big_cols);
+      const uint32_t n_big_tasks = n_big * per_big;
       uint32_t first[kSegClasses + 1];
       first[0] = n_big_tasks;
       for (int c = 0; c < kSegClasses; ++c) {
@@ -962,7 +984,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
         uint32_t t_next = 0;
         if (lane == 0) t_next = atomicAdd(&sh.next_task, 1u);
         if (t < n_big_tasks)
-          big_task(x, t / mtry, (int)(t % mtry), wl);
+          big_task(x, t / per_big, (int)(t % per_big) * a.big_cols, wl);
         else if (t < first[1])
           small_task<4>(x, sc.seg[0], t - first[0], sh.cnt[3], wl);
         else if (t < first[2])
@@ -1148,6 +1170,8 @@ struct Layout {
   uint32_t union_bytes;
   uint32_t wave_bytes;
   int32_t bstride;
+  int32_t big_stride;  // bins per large-node column histogram (a multiple of 4)
+  int32_t big_cols;    // large-node columns per wave task (the wave area holds that many histograms)
 };
 
 // A launch has wide nodes iff a tree's training set exceeds the wide limit.
@@ -1156,10 +1180,12 @@ bool wide_launch(const GrowConfig& cfg) { return cfg.n_cap > cfg.huge_min; }
 Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   Layout L;
   L.bstride = (std::max(cfg.bins_max, 1) + 63) / 64 * 64;
+  L.big_stride = (std::max(cfg.bins_max, 1) + 3) / 4 * 4;
   // a wave's histogram, or the staging of its small-node task (the rank task's
   // bins and candidates take 2880 + mtry bytes)
   const size_t wb = std::max(sizeof(WaveHist), (size_t)2880 + (size_t)mtry_max);
   L.wave_bytes = (uint32_t)((wb + 255) / 256 * 256);
+  L.big_cols = (int32_t)std::min<size_t>(4, L.wave_bytes / (8 * (size_t)L.big_stride));
   const size_t waves = (size_t)(cfg.block / kWave) * L.wave_bytes;
   const size_t draw = (size_t)std::min(cfg.block, 256) * (size_t)C;
   size_t wide = 0;
@@ -1267,6 +1293,8 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* cod
   a.union_bytes = L.union_bytes;
   a.wave_bytes = L.wave_bytes;
   a.bstride = L.bstride;
+  a.big_stride = L.big_stride;
+  a.big_cols = cfg.big_cols > 0 ? std::min(cfg.big_cols, L.big_cols) : L.big_cols;
   const void* kernel = grow_kernel_for(cfg, wide_launch(cfg));
   void* args[] = {&a};
   AIWC_HIP(hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, a.union_bytes, s));

@@ -156,6 +156,7 @@ struct GrowConfig {
   int block = 512;       // threads per workgroup
   int wg_per_cu = 0;     // 0 = as many as occupancy allows
   int occupancy = 4;     // waves per SIMD the kernel without the wide phase is built for (4, 5 or 6)
+  int big_cols = 0;      // candidate columns per large-node task, at most what the wave area holds (0 = all it holds)
   int huge_min = 4096;   // nodes with more in-bag rows are searched in workgroup-wide batches
   int wide_bytes = 0;    // LDS of a wide batch's histograms (0: 128 bytes per thread)
   int bins_max = 256;    // largest bin count of any column

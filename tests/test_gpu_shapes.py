@@ -26,12 +26,13 @@ def setup():
     return rf, ds, ob, of
 
 
-def fit_with(rf, ds, ob, env, flags=0):
+def fit_with(rf, ds, ob, env, flags=0, params=None):
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
         binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
-        return rf.aiwc_rf_fit(to_dev(ob.codes), binner, to_dev(ds.y), rf.make_params(6, 4, 3, True, 9), flags=flags)
+        prm = params if params is not None else rf.make_params(6, 4, 3, True, 9)
+        return rf.aiwc_rf_fit(to_dev(ob.codes), binner, to_dev(ds.y), prm, flags=flags)
     finally:
         for k, v in old.items():
             if v is None:
@@ -134,3 +135,25 @@ def test_occupancy_variants(setup, block, occ):
     f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": "100000", "AIWC_RF_GROW_OCC": occ})
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"block {block} occupancy {occ} tree {t}")
+
+
+@pytest.mark.parametrize("block", ["192", "1024"])
+@pytest.mark.parametrize("big_cols", ["1", "2", "3", "4"])
+def test_large_node_columns_per_task(block, big_cols):
+    """Large-node tasks taking 1 to 4 candidate columns each (mtry 7, so the
+    last task of a node takes fewer) grow the oracle's trees."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    log(f"large-node columns block={block} big_cols={big_cols}")
+    ds = synth.small(n_vec=700, n_devices=5, p_ln=8, p_u=6, seed=43)  # 3500 rows
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 100)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 4, 7, 1, seed=8)
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": "100000", "AIWC_RF_BIG_COLS": big_cols},
+                 params=rf.make_params(4, 7, 1, True, 8))
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"block {block} big_cols {big_cols} tree {t}")
