@@ -126,7 +126,8 @@ void aiwc_rf_binner_free(aiwc_rf_binner* binner);
 #define AIWC_RF_FIT_FUSED 0u /* grid: every tree of every forest in one persistent launch, captured in a hipGraph */
 #define AIWC_RF_FIT_PLAIN 1u /* grid: one launch sequence per forest (same results) */
 #define AIWC_RF_FIT_ASYNC 2u /* return after enqueueing; aiwc_rf_forest_wait() reports the status */
-#define AIWC_RF_FIT_TUNE 4u  /* pick the workgroup shape by timing the candidates on this call's first trees;
+#define AIWC_RF_FIT_TUNE 4u  /* pick the workgroup shape by timing the candidates on an evenly
+                                strided sample of this call's trees (up to 64 per CU);
                                 the choice is cached per problem shape (and in the file named by
                                 AIWC_RF_TUNE_CACHE, if set); results never depend on it */
 int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,

@@ -144,7 +144,21 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
   TuneKey key{device_info().cus, ilog2_ceil(base.n_cap), n_cols, base.bins_max, mtry_max, ilog2_ceil(n_tasks)};
   GrowConfig best = base;
   if (tune_lookup(key, &best)) return best;
-  const int64_t trial = std::min<int64_t>(n_tasks, 16LL * device_info().cus);
+  const int64_t trial = std::min<int64_t>(n_tasks, 64LL * device_info().cus);
+  // the trial grows an evenly strided sample of the launch's trees, so that a
+  // grid of forests is timed on all of its parameter triples and not only on
+  // its first forests (each sampled tree writes its own slots, which the fit
+  // overwrites)
+  const TreeTask* d_trial = F->d_tasks.p;
+  DevBuf<TreeTask> sample;
+  std::vector<TreeTask> h_sample;
+  if (trial < n_tasks) {
+    h_sample.resize((size_t)trial);
+    for (int64_t i = 0; i < trial; ++i) h_sample[(size_t)i] = F->tasks[(size_t)(i * n_tasks / trial)];
+    sample.reset((size_t)trial, s);
+    AIWC_HIP(hipMemcpyAsync(sample.p, h_sample.data(), sizeof(TreeTask) * (size_t)trial, hipMemcpyHostToDevice, s));
+    d_trial = sample.p;
+  }
   launch_init(F->status.p, nullptr, s);
   launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, codes_p, F->status.p, s);
   const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max);
@@ -165,7 +179,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
     for (int rep = 0; rep < 2; ++rep) {
       launch_init(nullptr, queue, s);
       AIWC_HIP(hipEventRecord(e0, s));
-      launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, F->d_tasks.p, (int32_t)trial,
+      launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, d_trial, (int32_t)trial,
                   F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p,
                   base.n_cap, mtry_max, grid, s);
       AIWC_HIP(hipEventRecord(e1, s));
@@ -181,6 +195,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  AIWC_HIP(hipStreamSynchronize(s));  // the sample's host copy is released here
   tune_store(key, best);
   return best;
 }
