@@ -36,7 +36,9 @@
 namespace aiwc {
 namespace {
 
-constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kHuge = 3, kSplit = 4;
+// kSplit: split, rows still to be partitioned; kSplitDone: split and already
+// partitioned by the wave that searched it (nodes of at most kSegMax rows)
+constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kHuge = 3, kSplit = 4, kSplitDone = 5;
 // Nodes with at most kSegMax in-bag rows are searched with their rows in a
 // lane segment of width 4, 8, 16, 32 or 64 (the smallest that holds them).
 constexpr uint32_t kSegMax = 64;
@@ -94,6 +96,8 @@ struct Scratch {
   uint8_t* dbin;
   uint32_t* dNL;
   int64_t* dSL;
+  uint32_t* dcnt;  // small split node k: entries that went left
+  uint64_t* dQL;   // small split node k: left side's sum of w y^2
   Cursor* cur;    // by split rank, when a level's do not fit the LDS
   uint4* chunks;  // partition work per 64-entry chunk: first entry, the node's end, split rank, column | bin << 8
   NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
@@ -131,6 +135,8 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   // a split node holds at least two rows, so a level has at most n/2 of them
   // and at most n/64 + n/2 chunks
   s->cur = reinterpret_cast<Cursor*>(take(sizeof(Cursor) * (n / 2 + 1)));
+  s->dcnt = reinterpret_cast<uint32_t*>(take(4 * n));
+  s->dQL = reinterpret_cast<uint64_t*>(take(8 * n));
   s->chunks = reinterpret_cast<uint4*>(take(sizeof(uint4) * (n / 64 + n / 2 + 2)));
   // class c holds nodes of more than 2 << c rows (c >= 1)
   for (int c = 0; c < kSegClasses; ++c)
@@ -259,6 +265,7 @@ struct Ctx {
   const TreeTask* T;
   Scratch sc;
   const uint64_t* buf;  // this level's entries
+  uint64_t* nbuf;       // the next level's entries
   const uint32_t* mstart;
   const uint32_t* mend;
   const uint32_t* mN;
@@ -282,21 +289,43 @@ __device__ __forceinline__ uint64_t pack_ns(uint32_t w, int64_t wy) { return ((u
 __device__ __forceinline__ uint32_t packed_n(uint64_t v) { return (uint32_t)((v + (1ull << 44)) >> 45); }
 __device__ __forceinline__ int64_t packed_s(uint64_t v, uint32_t n) { return (int64_t)(v - ((uint64_t)n << 45)); }
 
-// The left child's weight and sum of a small node from one segment
-// reduction, written by the segment's first lane with the decision.
+// The end of a small node's search, for the W lanes of its segment (one row
+// each, lane `sbase + r`): the left child's weight, sum and sum of w y^2 from
+// segment reductions, and the node's rows placed into its children's segments
+// of the next level (left ones first, in lane order, then the right ones), so
+// that the partition skips it; the segment's first lane writes the decision.
 template <int W>
-__device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node_ok, int r, bool split, uint32_t col,
-                                             uint32_t bin, bool left, uint32_t w, int64_t wy) {
-  const uint64_t acc = seg_sum<W>(left ? pack_ns(w, wy) : 0ull);
+__device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node_ok, int r, int sbase, bool split,
+                                             uint32_t col, uint32_t bin, bool valid, bool left, uint64_t e,
+                                             uint32_t start) {
+  const uint32_t w = entry_w(e);
+  const int64_t y = entry_y(e);
+  const int64_t wy = (int64_t)w * y;
+  uint64_t acc, QL;
+  if constexpr (W == kWave) {
+    acc = wave_sum(left ? pack_ns(w, wy) : 0ull);
+    QL = wave_sum(left ? (uint64_t)(wy * y) : 0ull);
+  } else {
+    acc = seg_sum<W>(left ? pack_ns(w, wy) : 0ull);
+    QL = seg_sum<W>(left ? (uint64_t)(wy * y) : 0ull);
+  }
   const uint32_t NL = packed_n(acc);
   const int64_t SL = packed_s(acc, NL);
+  const uint64_t seg = (W == kWave ? ~0ull : ((1ull << W) - 1ull)) << sbase;
+  const uint64_t lm = __ballot(left) & seg, rm = __ballot(split && valid && !left) & seg;
+  const uint64_t below = (1ull << lane_id()) - 1ull;
+  const uint32_t nl = (uint32_t)__popcll(lm);
+  if (split && valid)
+    x.nbuf[start + (left ? (uint32_t)__popcll(lm & below) : nl + (uint32_t)__popcll(rm & below))] = e;
   if (node_ok && r == 0) {
     if (split) {
       x.sc.dcol[k] = (uint8_t)col;
       x.sc.dbin[k] = (uint8_t)bin;
       x.sc.dNL[k] = NL;
       x.sc.dSL[k] = SL;
-      x.sc.status[k] = kSplit;
+      x.sc.dcnt[k] = nl;
+      x.sc.dQL[k] = QL;
+      x.sc.status[k] = kSplitDone;
     } else {
       x.sc.status[k] = kLeaf;
     }
@@ -378,7 +407,7 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   const bool split = node_ok && best >= 0.0 && best - parent_score(S, N) > 0.0;
   const uint32_t col = split ? cand[best_ib >> 8] : 0u, bin = best_ib & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
-  small_finish<W>(x, k, node_ok, r, split, col, bin, left, w, wy);
+  small_finish<W>(x, k, node_ok, r, sbase, split, col, bin, valid, left, e, start);
 }
 
 // Nodes of 33..64 rows: one node per wave, one row per lane.  Per candidate
@@ -464,20 +493,7 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   const bool split = am.score >= 0.0 && am.score - parent_score(S, N) > 0.0;
   const uint32_t col = split ? (uint32_t)s_cand[am.key >> 8] : 0u, bin = (uint32_t)am.key & 0xFF;
   const bool left = split && valid && rowp[col] <= bin;
-  const uint32_t NL = wave_sum(left ? w : 0u);
-  const int64_t SL = wave_sum(left ? wy : (int64_t)0);
-  if (lane == 0) {
-    if (split) {
-      x.sc.dcol[k] = (uint8_t)col;
-      x.sc.dbin[k] = (uint8_t)bin;
-      x.sc.dNL[k] = NL;
-      x.sc.dSL[k] = SL;
-      x.sc.status[k] = kSplit;
-    } else {
-      x.sc.status[k] = kLeaf;
-    }
-  }
-  wave_lds_sync();
+  small_finish<kWave>(x, k, true, lane, 0, split, col, bin, valid, left, e, start);
 }
 
 // Scan one column's histogram of packed bins (B <= 256 bins) with a wave: lane
@@ -912,7 +928,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     ++levels;
     const Level2 C = cur ? sc.L1 : sc.L0;  // this level
     const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
-    const Ctx x{&a, &T, sc, C.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
+    const Ctx x{&a, &T, sc, C.buf, X.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
     // (a) leaf rules, candidate draws, tiers
     if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
     if (tid == 0) sh.next_task = NW;
@@ -1013,10 +1029,12 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
       const uint32_t k = b0 + tid;
       const bool in = k < level_cnt;
-      const bool split = in && sc.status[k] == kSplit;
+      const uint8_t stk = in ? sc.status[k] : kLeaf;
+      const bool split = stk == kSplit || stk == kSplitDone;
       uint32_t total, ctotal;
       const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, sh.tmp, total) + n_split;
-      const uint32_t nch = split ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
+      // (the small nodes' rows were placed by their searches)
+      const uint32_t nch = stk == kSplit ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
       const uint32_t cfirst = block_exscan<BLOCK>(nch, sh.tmp, ctotal) + n_chunks;
       // (the bounds below hold by construction; the guards keep a broken
       // invariant from writing outside the scratch arrays)
@@ -1039,11 +1057,20 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
           }
           const uint32_t st = x.mstart[k], en = x.mend[k];
           work_part += en - st;
-          const Cursor c0{st, en, 0ull};
+          // a placed node's boundary is known; its cursor is marked done
+          const bool done = stk == kSplitDone;
+          const Cursor c0{done ? 0xFFFFFFFFu : st, en, 0ull};
           if (lds_cur)
             lcur[r] = c0;
           else
             sc.cur[r] = c0;
+          if (done) {
+            const uint32_t b = st + sc.dcnt[k];
+            const uint64_t QL = sc.dQL[k];
+            X.mend[2 * r] = b;
+            X.mstart[2 * r + 1] = b;
+            X.mQ[2 * r] = QL;
+          }
           const uint32_t NL = sc.dNL[k];
           const int64_t SL = sc.dSL[k];
           X.mstart[2 * r] = st;
@@ -1052,7 +1079,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
           X.mend[2 * r + 1] = en;
           X.mN[2 * r + 1] = N - NL;
           X.mS[2 * r + 1] = S - SL;
-          X.mQ[2 * r + 1] = x.mQ[k];  // the parent's, until the left side's is known
+          // the right side's: the parent's, less the left side's when known
+          X.mQ[2 * r + 1] = x.mQ[k] - (done ? sc.dQL[k] : 0ull);
         } else {
           a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
         }
@@ -1078,6 +1106,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     // (g) the boundary between each pair of children, and their sums of w y^2
     for (uint32_t r = tid; r < n_split; r += BLOCK) {
       const Cursor c = lds_cur ? lcur[r] : sc.cur[r];
+      if (c.L == 0xFFFFFFFFu) continue;  // placed by its search
       X.mend[2 * r] = c.L;
       X.mstart[2 * r + 1] = c.L;
       X.mQ[2 * r] = c.q;
