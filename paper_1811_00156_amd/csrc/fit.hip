@@ -96,6 +96,7 @@ struct Scratch {
   uint8_t* dbin;
   uint32_t* dNL;
   int64_t* dSL;
+  uint32_t* ridx;  // large node k: its index among the level's large (or wide) nodes
   uint32_t* dcnt;  // small split node k: entries that went left
   uint64_t* dQL;   // small split node k: left side's sum of w y^2
   Cursor* cur;    // by split rank, when a level's do not fit the LDS
@@ -136,6 +137,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   // and at most n/64 + n/2 chunks
   s->cur = reinterpret_cast<Cursor*>(take(sizeof(Cursor) * (n / 2 + 1)));
   s->dcnt = reinterpret_cast<uint32_t*>(take(4 * n));
+  s->ridx = reinterpret_cast<uint32_t*>(take(4 * n));
   s->dQL = reinterpret_cast<uint64_t*>(take(8 * n));
   s->chunks = reinterpret_cast<uint4*>(take(sizeof(uint4) * (n / 64 + n / 2 + 2)));
   // class c holds nodes of more than 2 << c rows (c >= 1)
@@ -203,6 +205,27 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* tmp, uint
   }
   __syncthreads();
   const uint32_t res = tmp[wid] + incl - v;
+  total = tmp[NW];
+  __syncthreads();
+  return res;
+}
+
+// The same for one u64 per thread (two counts packed in its halves).
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_exscan64(uint64_t v, uint64_t* tmp, uint64_t& total) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = (int)lane_id(), wid = threadIdx.x / kWave;
+  const uint64_t incl = wave_incl_scan<uint64_t>(v);
+  if (lane == kWave - 1) tmp[wid] = incl;
+  __syncthreads();
+  if (wid == 0) {
+    const uint64_t t = lane < NW ? tmp[lane] : 0ull;
+    const uint64_t ti = wave_incl_scan<uint64_t>(t);
+    if (lane < NW) tmp[lane] = ti - t;
+    if (lane == NW - 1) tmp[NW] = ti;
+  }
+  __syncthreads();
+  const uint64_t res = tmp[wid] + incl - v;
   total = tmp[NW];
   __syncthreads();
   return res;
@@ -603,9 +626,16 @@ __device__ __forceinline__ void big_task(const Ctx& x, uint32_t j, int ci0, Wave
   wave_lds_sync();
 }
 
-// Decide a node from its per-column records (columns ascending: keep the
-// first strictly greater score).
-__device__ __forceinline__ void decide_from_recs(const Ctx& x, uint32_t k, const Rec* recs, int mtry) {
+// A split decision: the column and bin, and the left child's weight and sum.
+struct Decision {
+  bool split;
+  uint32_t col, bin, NL;
+  int64_t SL;
+};
+
+// Decide a large or wide node from its per-column records (columns ascending:
+// keep the first strictly greater score).
+__device__ __forceinline__ Decision decide_from_recs(const Rec* recs, int mtry, int64_t S, uint32_t N) {
   double best = -1.0;
   int bi = -1;
   for (int i = 0; i < mtry; ++i) {
@@ -615,24 +645,19 @@ __device__ __forceinline__ void decide_from_recs(const Ctx& x, uint32_t k, const
       bi = i;
     }
   }
-  const int64_t S = x.mS[k];
-  const uint32_t N = x.mN[k];
+  Decision d{false, 0u, 0u, 0u, 0};
   if (bi >= 0 && best - parent_score(S, N) > 0.0) {
     const Rec r = recs[bi];
-    x.sc.dcol[k] = (uint8_t)(r.colbin >> 8);
-    x.sc.dbin[k] = (uint8_t)(r.colbin & 0xFF);
-    x.sc.dNL[k] = r.NL;
-    x.sc.dSL[k] = r.SL;
-    x.sc.status[k] = kSplit;
-  } else {
-    x.sc.status[k] = kLeaf;
+    d = Decision{true, r.colbin >> 8, r.colbin & 0xFFu, r.NL, r.SL};
   }
+  return d;
 }
 
 constexpr int kWideMax = 8;  // nodes per workgroup-wide batch
 
 struct Shared {
   uint32_t tmp[17];
+  uint64_t tmp64[17];
   uint64_t red[16];
   uint32_t cnt[3 + kSegClasses];  // [1] large, [2] wide, [3..] small nodes per segment width
   uint32_t task;
@@ -916,6 +941,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     sc.L0.mS[0] = S0;
     sc.L0.mQ[0] = Q0;
   }
+  if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
+  if (tid == 0) sh.next_task = NW;
   __syncthreads();
 
   // threads that draw candidates each own a C-byte row of the LDS union area
@@ -929,10 +956,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     const Level2 C = cur ? sc.L1 : sc.L0;  // this level
     const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
     const Ctx x{&a, &T, sc, C.buf, X.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
-    // (a) leaf rules, candidate draws, tiers
-    if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
-    if (tid == 0) sh.next_task = NW;
-    __syncthreads();
+    // (a) leaf rules, candidate draws, tiers (the tier counts and the task
+    // queue head were reset before the level began)
     if (tid < n_draw) {
       for (uint32_t k = tid; k < level_cnt; k += n_draw) {
         const uint32_t N = x.mN[k];
@@ -961,12 +986,15 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
           sc.status[k] = kBig;
           const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
           sc.big[j] = NodeDesc{k, st, len, N, S};
+          sc.ridx[k] = j;
           // each (node, column) task's column and bin count, ready for its wave
           const uint8_t* ck = sc.cand + (size_t)k * cand_stride(mtry);
           for (int i = 0; i < mtry; ++i) sc.btask[(size_t)j * mtry + i] = ck[i] | ((uint32_t)a.n_bins[ck[i]] << 8);
         } else {
           sc.status[k] = kHuge;
-          sc.huge[atomicAdd(&sh.cnt[2], 1u)] = NodeDesc{k, st, len, N, S};
+          const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
+          sc.huge[h] = NodeDesc{k, st, len, N, S};
+          sc.ridx[k] = h;
         }
       }
     }
@@ -1015,12 +1043,10 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
       }
     }
     __syncthreads();
-    // (d) decisions of the large and the wide nodes
-    for (uint32_t j = tid; j < n_big + (WIDE ? n_huge : 0u); j += BLOCK)
-      decide_from_recs(x, j < n_big ? sc.big[j].k : sc.huge[j - n_big].k, sc.recs + (size_t)j * mtry, mtry);
-    __syncthreads();
-    // (e) breadth-first child ids, node words, children's sums and cursors, and
-    // the partition's chunks of 64 entries of every split node.  The cursors
+    // (d) the large and wide nodes' decisions from their records (the wide
+    // nodes' records follow the large nodes'), then (e) breadth-first child
+    // ids, node words, children's sums and cursors, and the partition's chunks
+    // of 64 entries of every split node that is not placed yet.  The cursors
     // live in the LDS union area (free until the next level) when the level's
     // nodes fit it, else in scratch.
     const bool lds_cur = level_cnt <= a.union_bytes / (uint32_t)sizeof(Cursor);
@@ -1029,17 +1055,28 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
       const uint32_t k = b0 + tid;
       const bool in = k < level_cnt;
-      const uint8_t stk = in ? sc.status[k] : kLeaf;
+      uint8_t stk = in ? sc.status[k] : kLeaf;
+      Decision dc{false, 0u, 0u, 0u, 0};
+      if (stk == kBig || stk == kHuge) {
+        const uint32_t ri = sc.ridx[k] + (stk == kHuge ? n_big : 0u);
+        dc = decide_from_recs(sc.recs + (size_t)ri * mtry, mtry, x.mS[k], x.mN[k]);
+        stk = dc.split ? kSplit : kLeaf;
+      } else if (stk == kSplitDone) {
+        dc = Decision{true, sc.dcol[k], sc.dbin[k], sc.dNL[k], sc.dSL[k]};
+      }
       const bool split = stk == kSplit || stk == kSplitDone;
-      uint32_t total, ctotal;
-      const uint32_t r = block_exscan<BLOCK>(split ? 1u : 0u, sh.tmp, total) + n_split;
       // (the small nodes' rows were placed by their searches)
       const uint32_t nch = stk == kSplit ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
-      const uint32_t cfirst = block_exscan<BLOCK>(nch, sh.tmp, ctotal) + n_chunks;
+      // split ranks in the low half, chunk offsets in the high half
+      uint64_t tot;
+      const uint64_t ex = block_exscan64<BLOCK>((split ? 1ull : 0ull) | ((uint64_t)nch << 32), sh.tmp64, tot);
+      const uint32_t total = (uint32_t)tot, ctotal = (uint32_t)(tot >> 32);
+      const uint32_t r = (uint32_t)ex + n_split;
+      const uint32_t cfirst = (uint32_t)(ex >> 32) + n_chunks;
       // (the bounds below hold by construction; the guards keep a broken
       // invariant from writing outside the scratch arrays)
       if (nch > 0 && (uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2)) {
-        const uint32_t st = x.mstart[k], en = x.mend[k], cb = (uint32_t)sc.dcol[k] | ((uint32_t)sc.dbin[k] << 8);
+        const uint32_t st = x.mstart[k], en = x.mend[k], cb = dc.col | (dc.bin << 8);
         for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint4(st + c * kWave, en, r, cb);
       }
       if (in) {
@@ -1051,7 +1088,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
         } else if (split) {
           const uint32_t left = next_id + 2 * r;
           if ((int64_t)left + 1 < T.capacity) {
-            a.nodes[base_node + node] = node_split(sc.dcol[k], sc.dbin[k], left);
+            a.nodes[base_node + node] = node_split(dc.col, dc.bin, left);
           } else {
             atomicOr(a.status, kStatusCapacity);
           }
@@ -1071,8 +1108,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
             X.mstart[2 * r + 1] = b;
             X.mQ[2 * r] = QL;
           }
-          const uint32_t NL = sc.dNL[k];
-          const int64_t SL = sc.dSL[k];
+          const uint32_t NL = dc.NL;
+          const int64_t SL = dc.SL;
           X.mstart[2 * r] = st;
           X.mN[2 * r] = NL;
           X.mS[2 * r] = SL;
@@ -1112,6 +1149,9 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
       X.mQ[2 * r] = c.q;
       X.mQ[2 * r + 1] -= c.q;
     }
+    // the next level's tier counts and task queue head
+    if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
+    if (tid == 0) sh.next_task = NW;
     __syncthreads();
     level_lo = next_id;
     level_cnt = 2 * n_split;
