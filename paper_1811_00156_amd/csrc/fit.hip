@@ -249,9 +249,10 @@ __device__ __forceinline__ T block_sum(T v, T* tmp) {
 // mtry-1 of the stream (seed, tag 1, node, tree); position k swaps with
 // k + floor(r_k (C-k) / 2^64).  `perm` is this thread's C-entry LDS row
 // (stride `pst` bytes between entries).  The chosen columns are written
-// ascending to `out`.
+// ascending to `out`, and, when `bt` is given, column | bin count << 8 to
+// bt[0 .. mtry) (`nb`: the bin counts, in LDS).
 __device__ __forceinline__ void draw_candidates(uint8_t* perm, int pst, uint64_t seed, uint32_t node, uint32_t tree, int C, int mtry,
-                                uint8_t* out) {
+                                uint8_t* out, uint32_t* bt, const uint16_t* nb) {
   for (int c = 0; c < C; ++c) perm[c * pst] = (uint8_t)c;
   uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
   for (int b = 0; 4 * b < mtry; ++b) {
@@ -275,12 +276,18 @@ __device__ __forceinline__ void draw_candidates(uint8_t* perm, int pst, uint64_t
     }
   }
   int i = 0;
-  for (uint64_t m = m0; m; m &= m - 1) out[i++] = (uint8_t)__builtin_ctzll(m);
-  for (uint64_t m = m1; m; m &= m - 1) out[i++] = (uint8_t)(64 + __builtin_ctzll(m));
-  for (uint64_t m = m2; m; m &= m - 1) out[i++] = (uint8_t)(128 + __builtin_ctzll(m));
-  for (uint64_t m = m3; m; m &= m - 1) out[i++] = (uint8_t)(192 + __builtin_ctzll(m));
-  const uint8_t last = out[mtry - 1];
-  for (; i < cand_stride(mtry); ++i) out[i] = last;
+  uint32_t last = 0;
+  auto put = [&](uint32_t c) {
+    out[i] = (uint8_t)c;
+    if (bt) bt[i] = c | ((uint32_t)nb[c] << 8);
+    ++i;
+    last = c;
+  };
+  for (uint64_t m = m0; m; m &= m - 1) put((uint32_t)__builtin_ctzll(m));
+  for (uint64_t m = m1; m; m &= m - 1) put(64u + (uint32_t)__builtin_ctzll(m));
+  for (uint64_t m = m2; m; m &= m - 1) put(128u + (uint32_t)__builtin_ctzll(m));
+  for (uint64_t m = m3; m; m &= m - 1) put(192u + (uint32_t)__builtin_ctzll(m));
+  for (; i < cand_stride(mtry); ++i) out[i] = (uint8_t)last;
 }
 
 struct Ctx {
@@ -656,6 +663,7 @@ __device__ __forceinline__ Decision decide_from_recs(const Rec* recs, int mtry, 
 constexpr int kWideMax = 8;  // nodes per workgroup-wide batch
 
 struct Shared {
+  uint16_t nbins[256];  // bin count of every column
   uint32_t tmp[17];
   uint64_t tmp64[17];
   uint64_t red[16];
@@ -969,10 +977,9 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
           sc.status[k] = kLeaf;
           continue;
         }
-        draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
-                        sc.cand + (size_t)k * cand_stride(mtry));
         work_rows += len;
         ++work_nodes;
+        uint32_t* bt = nullptr;
         if (len <= kSegMax) {
           const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
           sc.status[k] = kSmall;
@@ -987,15 +994,15 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
           const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
           sc.big[j] = NodeDesc{k, st, len, N, S};
           sc.ridx[k] = j;
-          // each (node, column) task's column and bin count, ready for its wave
-          const uint8_t* ck = sc.cand + (size_t)k * cand_stride(mtry);
-          for (int i = 0; i < mtry; ++i) sc.btask[(size_t)j * mtry + i] = ck[i] | ((uint32_t)a.n_bins[ck[i]] << 8);
+          bt = sc.btask + (size_t)j * mtry;  // each (node, column) task's column and bin count
         } else {
           sc.status[k] = kHuge;
           const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
           sc.huge[h] = NodeDesc{k, st, len, N, S};
           sc.ridx[k] = h;
         }
+        draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                        sc.cand + (size_t)k * cand_stride(mtry), bt, sh.nbins);
       }
     }
     __syncthreads();
@@ -1181,6 +1188,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) vo
   __shared__ Shared sh;
   Scratch sc;
   carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max);
+  for (int c = threadIdx.x; c < a.C; c += BLOCK) sh.nbins[c] = (uint16_t)a.n_bins[c];
   for (;;) {
     if (threadIdx.x == 0) sh.task = atomicAdd(a.queue, 1u);
     __syncthreads();
