@@ -157,3 +157,44 @@ def test_large_node_columns_per_task(block, big_cols):
                  params=rf.make_params(4, 7, 1, True, 8))
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"block {block} big_cols {big_cols} tree {t}")
+
+
+@pytest.mark.parametrize("big_cols", ["2", "4"])
+def test_large_node_columns_with_256_bins(setup, big_cols):
+    """With 256-bin columns a wave's LDS area holds two large-node histograms,
+    so a request for four columns per task takes two; the trees still match."""
+    rf, ds, ob, of = setup
+    assert max(ob.n_bins) > 152
+    log(f"large-node columns 256 bins big_cols={big_cols}")
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": "192", "AIWC_RF_HUGE_MIN": "100000", "AIWC_RF_BIG_COLS": big_cols})
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"256 bins big_cols {big_cols} tree {t}")
+
+
+def test_partition_cursors_in_global_memory():
+    """A level with more nodes than a 192-thread workgroup's LDS area holds
+    cursors for (about 900) keeps its partition cursors in global memory; a deep
+    tree on 60000 rows has such levels, and still matches the oracle."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    log("global partition cursors")
+    ds = synth.small(n_vec=10000, n_devices=6, p_ln=6, p_u=4, seed=47)  # 60000 rows
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 64)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 2, 5, 1, seed=12)
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": "192", "AIWC_RF_HUGE_MIN": "100000"},
+                 params=rf.make_params(2, 5, 1, True, 12))
+    # some level holds far more than 900 nodes (the widest about 10000)
+    widest = 0
+    for t in range(2):
+        left, level = of.tree(t)["left"], [0]
+        while level:
+            widest = max(widest, len(level))
+            level = [c for k in level if left[k] >= 0 for c in (left[k], left[k] + 1)]
+    assert widest > 4 * 900, widest
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"global cursors tree {t}")
