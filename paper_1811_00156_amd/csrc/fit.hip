@@ -527,18 +527,20 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
 }
 
 // Scan one column's histogram of packed bins (B <= 256 bins) with a wave: lane
-// l owns bins [4l, 4l + 4); prefix sums give the left side of every split
-// b <= B-2.  Returns the wave's best (max score, lowest bin) in every lane; the
-// left sums oNL, oSL of that split are valid in lane `am.lane`.
+// l owns bins [l q, l q + q) with q = ceil(B / 64) (so a 64-bin column takes one
+// bin per lane); prefix sums give the left side of every split b <= B-2.
+// Returns the wave's best (max score, lowest bin) in every lane; the left sums
+// oNL, oSL of that split are valid in lane `am.lane`.
 __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_t N, int64_t S, uint32_t& oNL,
                                               int64_t& oSL) {
   const int lane = (int)lane_id();
-  const int b0 = lane * 4;
+  const int q = (B + kWave - 1) / kWave;
+  const int b0 = lane * q;
   uint64_t h[4];
   uint64_t loc = 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    h[u] = b0 + u < B ? hv[b0 + u] : 0ull;
+    h[u] = u < q && b0 + u < B ? hv[b0 + u] : 0ull;
     loc += h[u];
   }
   uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
@@ -550,7 +552,7 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
   for (int u = 0; u < 4; ++u) {
     const int b = b0 + u;
     // an empty bin repeats the previous split, which already won any tie
-    if (h[u] == 0) continue;
+    if (u >= q || h[u] == 0) continue;
     v += h[u];
     const uint32_t NL = packed_n(v);
     if (b <= B - 2 && NL < N) {
@@ -813,7 +815,7 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
           rc.colbin = ((uint32_t)c << 8) | (uint32_t)(am.score >= 0.0 ? am.key : 0);
           x.sc.recs[(size_t)(rec_base + h0 + j) * mtry + c0 + i] = rc;
         }
-        // zero the bins this lane read (lane l scans bins 4l .. 4l + 3)
+        // zero the column's bins, four per lane (the scan's reads are done)
         if (4 * lane < B) *reinterpret_cast<uint4*>(hv + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
         if (4 * lane + 2 < B) *reinterpret_cast<uint4*>(hv + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
       }
