@@ -430,7 +430,7 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     AIWC_HIP(hipMemcpyAsync(F->test_rows.p, L.test_rows.data(), sizeof(int32_t) * L.test_rows.size(),
                             hipMemcpyHostToDevice, s));
   DevBuf<int64_t> y_fp((size_t)n, s);
-  DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte row reads
+  DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte reads of the last row
   DevBuf<uint32_t> queue(1, s);
 
   GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);

@@ -161,8 +161,12 @@ struct WaveHist {
 struct GrowArgs {
   const uint8_t* codes;
   int32_t C;
-  const uint8_t* codes_p;  // the same codes, rows padded to Cp (a multiple of 16) bytes
+  const uint8_t* codes_p;  // the same codes, rows padded to Cp bytes (one cache line holds whole rows)
   int32_t Cp;
+  // the copy the searches and the partition gather codes from: the dense rows
+  // while the training set's codes fit an L2 comfortably, else the padded ones
+  const uint8_t* rcodes;
+  int32_t rC;
   const int32_t* n_bins;
   const int64_t* y_fp;
   const int32_t* train_rows;
@@ -386,7 +390,7 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   uint64_t* s_pv = reinterpret_cast<uint64_t*>(area);  // [64] packed (w, w y)
   uint8_t* s_codes = area + 512;                       // [64 columns][64 lanes]
   s_pv[lane] = pack_ns(w, wy);
-  const uint8_t* rowp = a.codes + (size_t)row * a.C;
+  const uint8_t* rowp = a.rcodes + (size_t)row * a.rC;
   const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
 
   // each lane keeps its own best split (score, candidate index, bin) over the
@@ -459,7 +463,7 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   const int64_t y = entry_y(e);
   const int64_t wy = (int64_t)w * y;
   const uint64_t pv = pack_ns(w, wy);
-  const uint8_t* rowp = a.codes + (size_t)entry_row(e) * a.C;
+  const uint8_t* rowp = a.rcodes + (size_t)entry_row(e) * a.rC;
   const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
   uint64_t* hv = reinterpret_cast<uint64_t*>(area);            // [256] packed bins by code
@@ -601,7 +605,7 @@ __device__ __forceinline__ void big_task(const Ctx& x, uint32_t j, int ci0, Wave
     for (int u = 0; u < U; ++u) e[u] = p0 + u * kWave < end ? x.buf[p0 + u * kWave] : 0ull;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint8_t* rp = a.codes + (size_t)entry_row(e[u]) * a.C;
+      const uint8_t* rp = a.rcodes + (size_t)entry_row(e[u]) * a.rC;
 #pragma unroll
       for (int g = 0; g < G; ++g) code[u][g] = (g < gn && p0 + u * kWave < end) ? rp[c[g]] : 0u;
     }
@@ -702,8 +706,9 @@ __device__ __forceinline__ void wide_setup(const Ctx& x, const NodeDesc* list, i
 
 // The wide nodes of a level, nb at a time.  Node j of a batch has its rows cut
 // into chunks of 64, one wave per chunk, so the candidate columns are uniform
-// across a wave.  Each lane reads its row's entry once and, when the padded
-// code rows fit 80 bytes, the whole code row with five 16-byte loads; the
+// across a wave.  Each lane reads its row's entry once and, when a row has at
+// most 80 codes, the first 80 bytes of its padded code row with five 16-byte
+// loads; the
 // candidate codes are picked from registers and each is added to the packed
 // bin of its (node, column) histogram (hc columns at a time when they do not
 // all fit the LDS).  One wave per (node, column) then scans, writes the
@@ -719,7 +724,7 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
   const int cst = (mtry + 7) & ~7;
   const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
   uint64_t* H = reinterpret_cast<uint64_t*>(lds);
-  const bool row_regs = a.Cp <= 80;
+  const bool row_regs = a.C <= 80;
   // the histograms start zeroed; each scan zeroes what it read
   for (uint32_t i = 2 * tid; i < a.union_bytes / 8; i += 2 * BLOCK)
     *reinterpret_cast<uint4*>(H + i) = make_uint4(0u, 0u, 0u, 0u);
@@ -785,7 +790,7 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
             }
           }
         } else {
-          const uint8_t* rp = a.codes + (size_t)row * a.C;
+          const uint8_t* rp = a.rcodes + (size_t)row * a.rC;
           for (int i0 = 0; i0 < nc; i0 += 8) {
             const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
             uint32_t cd[8];
@@ -858,7 +863,7 @@ __device__ __forceinline__ void partition_level(const Ctx& x, uint64_t* __restri
     }
 #pragma unroll
     for (int u = 0; u < UP; ++u)
-      go_left[u] = mv[u] && a.codes[(size_t)entry_row(e[u]) * a.C + col[u]] <= bin[u];
+      go_left[u] = mv[u] && a.rcodes[(size_t)entry_row(e[u]) * a.rC + col[u]] <= bin[u];
 #pragma unroll
     for (int u = 0; u < UP; ++u) {
       if (c0 + (uint32_t)(u * NW) >= n_chunks) break;
@@ -1351,6 +1356,9 @@ void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* cod
   a.C = C;
   a.codes_p = codes_p;
   a.Cp = padded_cols(C);
+  const bool dense = n_cap * (int64_t)C <= (int64_t)1 << 20;
+  a.rcodes = dense ? codes : codes_p;
+  a.rC = dense ? C : a.Cp;
   a.n_bins = d_n_bins;
   a.y_fp = y_fp;
   a.train_rows = train_rows;

@@ -183,7 +183,17 @@ void launch_set_i32(int32_t* p, int32_t v, hipStream_t s);
 // Validates y and the codes, writes y_fp and a copy of the codes whose rows are
 // padded to padded_cols(C) bytes (16-byte aligned rows); the copy's buffer must
 // hold 64 bytes more than n * padded_cols(C), read but never used.
-inline int32_t padded_cols(int32_t C) { return (C + 15) / 16 * 16; }
+// Row stride of the padded code copy: a divisor of the 128-byte cache line
+// (16, 32, 64 or 128 bytes) or a multiple of it, so that no row straddles two
+// lines and a row's codes arrive with one line fetch.
+inline int32_t padded_cols(int32_t C) {
+  if (C <= 128) {
+    int32_t p = 16;
+    while (p < C) p *= 2;
+    return p;
+  }
+  return (C + 127) / 128 * 128;
+}
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
                     int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s);
 size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);

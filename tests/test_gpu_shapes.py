@@ -198,3 +198,27 @@ def test_partition_cursors_in_global_memory():
     assert widest > 4 * 900, widest
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"global cursors tree {t}")
+
+
+@pytest.mark.parametrize("p_ln,p_u,n_vec", [(40, 20, 4000), (60, 40, 2400)])
+@pytest.mark.parametrize("huge_min", ["64", "100000"])
+def test_line_aligned_code_rows(p_ln, p_u, n_vec, huge_min):
+    """Training sets whose codes exceed 1 MB are gathered from the copy whose
+    rows are padded to a cache-line divisor or multiple (64 bytes for 61
+    columns, 128 for 101): the trees still match the oracle."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1811_00156_amd import rf
+
+    ds = synth.small(n_vec=n_vec, n_devices=5, p_ln=p_ln, p_u=p_u, seed=53)
+    assert ds.n * (ds.X.shape[1] + 1) > 1 << 20
+    log(f"line-aligned rows {ds.n} x {ds.X.shape[1] + 1} huge_min={huge_min}")
+    ob = O.bin(ds.X, ds.device, ds.n_devices, 256)
+    of = O.fit(ob.codes, ob.n_bins, ds.y, 2, 20, 2, seed=14)
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": "512", "AIWC_RF_HUGE_MIN": huge_min},
+                 params=rf.make_params(2, 20, 2, True, 14))
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"line-aligned rows huge_min {huge_min} tree {t}")
