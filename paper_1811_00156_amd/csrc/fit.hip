@@ -885,6 +885,27 @@ __device__ __forceinline__ void partition_level(const Ctx& x, uint64_t* __restri
   }
 }
 
+// Bootstrap multiplicities of a tree's n training rows into cnt[0 .. n): n
+// draws with replacement, draw i = floor(r_i n / 2^64) for the words r_i of
+// the Philox stream (seed, tag 0, 0, tree) (every row once without
+// bootstrap).  `cnt` is in LDS or in global memory (inlined once for each).
+template <int BLOCK>
+__device__ __forceinline__ void bootstrap_counts(const TreeTask& T, int64_t n, uint32_t* cnt) {
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < n; i += BLOCK) cnt[i] = T.bootstrap ? 0u : 1u;
+  __syncthreads();
+  if (T.bootstrap) {
+    const int64_t nblk = (n + 3) / 4;
+    for (int64_t b = tid; b < nblk; b += BLOCK) {
+      const U64x4 r = philox4x64_10((uint64_t)b, kTagBootstrap, 0, (uint64_t)T.tree, T.seed, 0);
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        if (4 * b + w < n) atomicAdd(&cnt[scale_draw(r.w[w], (uint64_t)n)], 1u);
+    }
+    __syncthreads();
+  }
+}
+
 // WIDE: the launch may hold nodes above the wide limit (the kernel without
 // the wide-batch phase is compiled separately, so that small training sets
 // keep its leaner register allocation).
@@ -897,19 +918,14 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
   const int32_t* train = T.train_off >= 0 ? a.train_rows + T.train_off : nullptr;
   const int mtry = T.mtry;
 
-  // 1. bootstrap multiplicities
-  for (int64_t i = tid; i < n; i += BLOCK) sc.cnt[i] = T.bootstrap ? 0u : 1u;
-  __syncthreads();
-  if (T.bootstrap) {
-    const int64_t nblk = (n + 3) / 4;
-    for (int64_t b = tid; b < nblk; b += BLOCK) {
-      const U64x4 r = philox4x64_10((uint64_t)b, kTagBootstrap, 0, (uint64_t)T.tree, T.seed, 0);
-#pragma unroll
-      for (int w = 0; w < 4; ++w)
-        if (4 * b + w < n) atomicAdd(&sc.cnt[scale_draw(r.w[w], (uint64_t)n)], 1u);
-    }
-    __syncthreads();
-  }
+  // 1. bootstrap multiplicities, counted in the LDS union area (free until the
+  // first level) when the training set fits it, else in scratch
+  const bool lds_cnt = n <= (int64_t)(a.union_bytes / 4u);
+  uint32_t* const cnt_lds = reinterpret_cast<uint32_t*>(lds);
+  if (lds_cnt)
+    bootstrap_counts<BLOCK>(T, n, cnt_lds);
+  else
+    bootstrap_counts<BLOCK>(T, n, sc.cnt);
   // in-bag entries and root sums; each thread takes eight rows per pass,
   // strided by the block, so a pass costs one workgroup scan (the order of the
   // entries is free: every later sum over them is exact)
@@ -923,7 +939,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t i = base + (int64_t)r * BLOCK + tid;
-      c[r] = i < n ? sc.cnt[i] : 0u;
+      c[r] = i < n ? (lds_cnt ? cnt_lds[i] : sc.cnt[i]) : 0u;
       mine += c[r] > 0 ? 1u : 0u;
       // in-bag bitmap: this wave's 64 consecutive rows form one word
       const uint64_t bits = __ballot(c[r] > 0);
