@@ -363,8 +363,13 @@ def bench_serve(args):
     arr, reqs = stream(1000.0)
     log("serve warmup")
     serve(arr, reqs[:200], open_loop=False)
-    log("serve saturated")
-    sat = serve(arr, reqs, open_loop=False)
+    # saturated: the median of three closed-loop passes (one pass is short, and
+    # its host-side submission varies from run to run)
+    sats = []
+    for i in range(3):
+        log(f"serve saturated {i}")
+        sats.append(serve(arr, reqs, open_loop=False))
+    sat = sorted(sats, key=lambda d: d["rows_per_s"])[1]
     mean_rows = np.mean([r.shape[0] for r in reqs])
     points = {}
     for frac in (0.25, 0.5, 0.8):
@@ -381,7 +386,7 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": "c5: serving the c3 forest (500 trees, 65 columns); Poisson arrivals, "
                                "1..4096 rows per request (log-uniform)", "requests": n_req},
-        "saturated": sat, "load_points": points,
+        "saturated": sat, "saturated_rows_per_s_runs": [d["rows_per_s"] for d in sats], "load_points": points,
     }
 
 
