@@ -407,7 +407,7 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   F->work.reset((size_t)n_tasks * 4, s);
   F->node_base.reset((size_t)n_tasks, s);
   F->status.reset(1, s);
-  AIWC_HIP(hipHostMalloc((void**)&F->status_host, sizeof(uint32_t), hipHostMallocDefault));
+  F->status_host = pinned_word_acquire();
   *F->status_host = 0;
   AIWC_HIP(hipEventCreateWithFlags(&F->done, hipEventDisableTiming));
   AIWC_HIP(hipEventCreate(&F->grow_begin));
@@ -415,10 +415,9 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   {
     std::vector<int64_t> bases((size_t)n_tasks);
     for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
-    AIWC_HIP(hipMemcpyAsync(F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * n_tasks, hipMemcpyHostToDevice, s));
-    AIWC_HIP(hipMemcpyAsync(F->node_base.p, bases.data(), sizeof(int64_t) * n_tasks, hipMemcpyHostToDevice, s));
-    // the staging copies above read pageable host memory; wait before it goes out of scope
-    AIWC_HIP(hipStreamSynchronize(s));
+    const HostPart parts[2] = {{F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * (size_t)n_tasks},
+                               {F->node_base.p, bases.data(), sizeof(int64_t) * (size_t)n_tasks}};
+    upload_staged(s, parts, 2);
   }
   F->train_rows.reset(train_rows.size(), s);
   DevBuf<int32_t>& d_train = F->train_rows;
@@ -699,7 +698,7 @@ void aiwc_rf_forest_free(aiwc_rf_forest* f) {
   if (f->done) (void)hipEventDestroy(f->done);
   if (f->grow_begin) (void)hipEventDestroy(f->grow_begin);
   if (f->grow_end) (void)hipEventDestroy(f->grow_end);
-  if (f->status_host) (void)hipHostFree(f->status_host);
+  pinned_word_release(f->status_host);
   delete f;
 }
 

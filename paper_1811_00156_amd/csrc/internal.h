@@ -33,6 +33,22 @@ void* dev_alloc(size_t bytes, hipStream_t stream);
 void dev_release(void* p, hipStream_t stream);
 void dev_cache_trim();  // hand every cached block back to HIP
 
+// Host-to-device copies of host buffers through one pinned staging buffer per
+// device: the sources are copied into it on the host, its copies to `dst` are
+// enqueued on `stream`, and the call returns without waiting for them (a later
+// call waits for them before it reuses the buffer).
+struct HostPart {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+void upload_staged(hipStream_t stream, const HostPart* parts, int n_parts);
+
+// A pinned host word for a forest's status, from a process-wide pool (or its
+// own pinned allocation when the pool is exhausted); release hands it back.
+uint32_t* pinned_word_acquire();
+void pinned_word_release(uint32_t* p);
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;

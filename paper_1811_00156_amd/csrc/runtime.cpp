@@ -1,5 +1,6 @@
 // Host runtime of libaiwc_rf: errors, device properties and the device memory
 // cache that every allocation of the library goes through.
+#include <algorithm>
 #include <array>
 #include <cstdio>
 #include <cstdlib>
@@ -7,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "internal.h"
 
@@ -133,6 +135,99 @@ void dev_release(void* p, hipStream_t stream) {
   (void)hipEventRecord(b.ready, stream);
   if (prev != b.device) (void)hipSetDevice(prev);
   c.free_blocks.emplace(b.bytes, b);
+}
+
+namespace {
+
+struct Staging {
+  std::mutex mu;
+  uint8_t* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t last = nullptr;  // the last copies out of the buffer
+};
+
+Staging& staging(int dev) {
+  static std::mutex mu;
+  static std::map<int, Staging> per_device;
+  std::lock_guard<std::mutex> g(mu);
+  return per_device[dev];
+}
+
+struct WordPool {
+  std::mutex mu;
+  uint32_t* block = nullptr;
+  std::vector<uint32_t*> free_words;
+};
+
+WordPool& word_pool() {
+  static WordPool w;
+  return w;
+}
+
+constexpr int kPinnedWords = 4096;
+
+}  // namespace
+
+void upload_staged(hipStream_t stream, const HostPart* parts, int n_parts) {
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  Staging& st = staging(dev);
+  std::lock_guard<std::mutex> g(st.mu);
+  size_t total = 0;
+  for (int i = 0; i < n_parts; ++i) total += (parts[i].bytes + 255) / 256 * 256;
+  if (total == 0) return;
+  if (st.last) AIWC_HIP(hipEventSynchronize(st.last));  // the buffer's previous copies are done
+  if (total > st.cap) {
+    if (st.p) AIWC_HIP(hipHostFree(st.p));
+    st.p = nullptr;
+    st.cap = 0;
+    const size_t cap = std::max(total, (size_t)1 << 20);
+    AIWC_HIP(hipHostMalloc((void**)&st.p, cap, hipHostMallocDefault));
+    st.cap = cap;
+  }
+  if (!st.last) AIWC_HIP(hipEventCreateWithFlags(&st.last, hipEventDisableTiming));
+  size_t off = 0;
+  for (int i = 0; i < n_parts; ++i) {
+    if (parts[i].bytes == 0) continue;
+    std::memcpy(st.p + off, parts[i].src, parts[i].bytes);
+    AIWC_HIP(hipMemcpyAsync(parts[i].dst, st.p + off, parts[i].bytes, hipMemcpyHostToDevice, stream));
+    off += (parts[i].bytes + 255) / 256 * 256;
+  }
+  AIWC_HIP(hipEventRecord(st.last, stream));
+}
+
+uint32_t* pinned_word_acquire() {
+  WordPool& w = word_pool();
+  {
+    std::lock_guard<std::mutex> g(w.mu);
+    if (!w.block) {
+      if (hipHostMalloc((void**)&w.block, sizeof(uint32_t) * kPinnedWords, hipHostMallocPortable) == hipSuccess) {
+        for (int i = kPinnedWords - 1; i >= 0; --i) w.free_words.push_back(w.block + i);
+      } else {
+        (void)hipGetLastError();
+        w.block = nullptr;
+      }
+    }
+    if (!w.free_words.empty()) {
+      uint32_t* p = w.free_words.back();
+      w.free_words.pop_back();
+      return p;
+    }
+  }
+  uint32_t* p = nullptr;
+  AIWC_HIP(hipHostMalloc((void**)&p, sizeof(uint32_t), hipHostMallocDefault));
+  return p;
+}
+
+void pinned_word_release(uint32_t* p) {
+  if (!p) return;
+  WordPool& w = word_pool();
+  std::lock_guard<std::mutex> g(w.mu);
+  if (w.block && p >= w.block && p < w.block + kPinnedWords) {
+    w.free_words.push_back(p);
+    return;
+  }
+  (void)hipHostFree(p);
 }
 
 void dev_cache_trim() {
