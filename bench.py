@@ -362,7 +362,7 @@ def bench_serve(args):
 
     arr, reqs = stream(1000.0)
     log("serve warmup")
-    serve(arr, reqs[:200], open_loop=False)
+    serve(arr, reqs, open_loop=False)
     # saturated: the median of three closed-loop passes (one pass is short, and
     # its host-side submission varies from run to run)
     sats = []
