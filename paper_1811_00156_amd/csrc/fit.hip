@@ -36,8 +36,9 @@
 namespace aiwc {
 namespace {
 
-// kSplit: split, rows still to be partitioned; kSplitDone: split and already
-// partitioned by the wave that searched it (nodes of at most kSegMax rows)
+// kSplitDone: split and already partitioned by the wave that searched it (nodes
+// of at most kSegMax rows); kSplit: a large or wide node decided to split in
+// the child-id step, its rows still to be partitioned (never stored)
 constexpr uint8_t kLeaf = 0, kSmall = 1, kBig = 2, kHuge = 3, kSplit = 4, kSplitDone = 5;
 // Nodes with at most kSegMax in-bag rows are searched with their rows in a
 // lane segment of width 4, 8, 16, 32 or 64 (the smallest that holds them).
@@ -92,7 +93,7 @@ struct Scratch {
   uint8_t* status;
   uint8_t* cand;     // level node k's candidate columns at k * cand_stride(mtry), ascending, padded
   uint32_t* btask;   // large node j's candidate i at j * mtry + i: column | bin count << 8
-  uint8_t* dcol;
+  uint8_t* dcol;  // small split node k's decision: column, bin, left weight and sum
   uint8_t* dbin;
   uint32_t* dNL;
   int64_t* dSL;
@@ -104,7 +105,7 @@ struct Scratch {
   NodeDesc* seg[kSegClasses];  // small nodes by segment width 4 << class
   NodeDesc* big;
   NodeDesc* huge;
-  Rec* recs;  // large node j's candidate i at j * mtry + i
+  Rec* recs;  // large node j's candidate i at j * mtry + i; wide node h's at (n_big + h) * mtry + i
 };
 
 __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max) {
