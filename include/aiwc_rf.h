@@ -129,7 +129,13 @@ void aiwc_rf_binner_free(aiwc_rf_binner* binner);
 #define AIWC_RF_FIT_TUNE 4u  /* pick the workgroup shape by timing the candidates on an evenly
                                 strided sample of this call's trees (up to 64 per CU);
                                 the choice is cached per problem shape (and in the file named by
-                                AIWC_RF_TUNE_CACHE, if set); results never depend on it */
+                                AIWC_RF_TUNE_CACHE, if set); results never depend on it.
+                                Without it the shape follows the problem size; the environment
+                                variables AIWC_RF_GROW_BLOCK (192, 256, 512 or 1024 threads),
+                                AIWC_RF_HUGE_MIN (rows above which a node is searched by the
+                                whole workgroup), AIWC_RF_GROW_OCC (4, 5 or 6 waves per SIMD),
+                                AIWC_RF_GROW_WG_PER_CU and AIWC_RF_BIG_COLS (1 to 4 columns per
+                                large-node task) override it, again without changing results */
 int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
                 const double* y_log10, const int8_t* fold_id, const aiwc_rf_params* params_host,
                 const int32_t* heldout_fold_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,
