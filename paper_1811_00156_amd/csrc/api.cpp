@@ -250,13 +250,10 @@ int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, 
     }
     launch_bin_encode(X, device_id, n, p, n_devices, b->d_n_bins.p, b->d_thresholds.p, codes, status.p, s);
     uint32_t st = 0;
-    AIWC_HIP(hipMemcpyAsync(&st, status.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (fit) {
-      AIWC_HIP(hipMemcpyAsync(b->n_bins.data(), b->d_n_bins.p, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s));
-      AIWC_HIP(hipMemcpyAsync(b->thresholds.data(), b->d_thresholds.p, sizeof(float) * (size_t)p * 255,
-                              hipMemcpyDeviceToHost, s));
-    }
-    AIWC_HIP(hipStreamSynchronize(s));
+    const DevicePart parts[3] = {{&st, status.p, sizeof(uint32_t)},
+                                 {b->n_bins.data(), b->d_n_bins.p, fit ? sizeof(int32_t) * (size_t)(p + 1) : 0},
+                                 {b->thresholds.data(), b->d_thresholds.p, fit ? sizeof(float) * (size_t)p * 255 : 0}};
+    download_staged(s, parts, 3);
     std::string msg;
     const int32_t code = status_to_code(st, msg);
     if (code != AIWC_RF_OK) fail(code, msg);

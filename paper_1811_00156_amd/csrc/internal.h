@@ -44,6 +44,16 @@ struct HostPart {
 };
 void upload_staged(hipStream_t stream, const HostPart* parts, int n_parts);
 
+// Device-to-host copies through a second pinned staging buffer per device:
+// enqueued on `stream`, then the stream is synchronized and the results are
+// copied to their host destinations.
+struct DevicePart {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+void download_staged(hipStream_t stream, const DevicePart* parts, int n_parts);
+
 // A pinned host word for a forest's status, from a process-wide pool (or its
 // own pinned allocation when the pool is exhausted); release hands it back.
 uint32_t* pinned_word_acquire();

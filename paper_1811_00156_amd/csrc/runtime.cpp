@@ -146,11 +146,23 @@ struct Staging {
   hipEvent_t last = nullptr;  // the last copies out of the buffer
 };
 
-Staging& staging(int dev) {
+Staging& staging(int dev, bool down = false) {
   static std::mutex mu;
-  static std::map<int, Staging> per_device;
+  static std::map<int, Staging> per_device, per_device_down;
   std::lock_guard<std::mutex> g(mu);
-  return per_device[dev];
+  return down ? per_device_down[dev] : per_device[dev];
+}
+
+// Makes st.p hold at least `total` bytes (the caller holds st.mu and no copy
+// into or out of the buffer is pending).
+void staging_reserve(Staging& st, size_t total) {
+  if (total <= st.cap) return;
+  if (st.p) AIWC_HIP(hipHostFree(st.p));
+  st.p = nullptr;
+  st.cap = 0;
+  const size_t cap = std::max(total, (size_t)1 << 20);
+  AIWC_HIP(hipHostMalloc((void**)&st.p, cap, hipHostMallocDefault));
+  st.cap = cap;
 }
 
 struct WordPool {
@@ -177,14 +189,7 @@ void upload_staged(hipStream_t stream, const HostPart* parts, int n_parts) {
   for (int i = 0; i < n_parts; ++i) total += (parts[i].bytes + 255) / 256 * 256;
   if (total == 0) return;
   if (st.last) AIWC_HIP(hipEventSynchronize(st.last));  // the buffer's previous copies are done
-  if (total > st.cap) {
-    if (st.p) AIWC_HIP(hipHostFree(st.p));
-    st.p = nullptr;
-    st.cap = 0;
-    const size_t cap = std::max(total, (size_t)1 << 20);
-    AIWC_HIP(hipHostMalloc((void**)&st.p, cap, hipHostMallocDefault));
-    st.cap = cap;
-  }
+  staging_reserve(st, total);
   if (!st.last) AIWC_HIP(hipEventCreateWithFlags(&st.last, hipEventDisableTiming));
   size_t off = 0;
   for (int i = 0; i < n_parts; ++i) {
@@ -194,6 +199,28 @@ void upload_staged(hipStream_t stream, const HostPart* parts, int n_parts) {
     off += (parts[i].bytes + 255) / 256 * 256;
   }
   AIWC_HIP(hipEventRecord(st.last, stream));
+}
+
+void download_staged(hipStream_t stream, const DevicePart* parts, int n_parts) {
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  Staging& st = staging(dev, true);
+  std::lock_guard<std::mutex> g(st.mu);
+  size_t total = 0;
+  for (int i = 0; i < n_parts; ++i) total += (parts[i].bytes + 255) / 256 * 256;
+  if (total == 0) return;
+  staging_reserve(st, total);
+  size_t off = 0;
+  for (int i = 0; i < n_parts; ++i) {
+    if (parts[i].bytes) AIWC_HIP(hipMemcpyAsync(st.p + off, parts[i].src, parts[i].bytes, hipMemcpyDeviceToHost, stream));
+    off += (parts[i].bytes + 255) / 256 * 256;
+  }
+  AIWC_HIP(hipStreamSynchronize(stream));
+  off = 0;
+  for (int i = 0; i < n_parts; ++i) {
+    if (parts[i].bytes) std::memcpy(parts[i].dst, st.p + off, parts[i].bytes);
+    off += (parts[i].bytes + 255) / 256 * 256;
+  }
 }
 
 uint32_t* pinned_word_acquire() {
