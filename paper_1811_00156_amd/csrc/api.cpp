@@ -72,9 +72,9 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   // workgroup-wide batches; small ones: 512 threads per tree while trees are
   // few, and once there are enough trees to fill several workgroups per CU,
   // 192 threads at 6 waves per SIMD (eight resident trees per CU).  A
-  // large-node task takes one candidate column while trees are few (more
-  // waves per tree), up to four once the CUs are full.
-  cfg.big_cols = 1;
+  // large-node task takes two candidate columns while trees are few (more
+  // tasks per node for the tree's waves), up to four once the CUs are full.
+  cfg.big_cols = 2;
   if (n_cap > 16384) {
     cfg.block = 512;
     cfg.huge_min = 64;
