@@ -51,10 +51,11 @@ extern "C" {
 
 /* Limits.  Rows: the fixed-point budget keeps |S| <= 2^40 and Q <= 2^62 exact. */
 #define AIWC_RF_MAX_ROWS (1 << 18)
-#define AIWC_RF_MAX_FEATURES 255
+#define AIWC_RF_LEAF 255 /* column value that marks a leaf in node words and exported node arrays */
+#define AIWC_RF_MAX_COLS 255 /* code columns (features + device): column ids stay below AIWC_RF_LEAF */
+#define AIWC_RF_MAX_FEATURES (AIWC_RF_MAX_COLS - 1)
 #define AIWC_RF_MAX_BINS 256
 #define AIWC_RF_MAX_TREES (1 << 14)
-#define AIWC_RF_LEAF 255 /* column value that marks a leaf in exported node arrays */
 
 typedef struct aiwc_rf_binner aiwc_rf_binner; /* per-column thresholds and bin counts */
 typedef struct aiwc_rf_forest aiwc_rf_forest; /* one or many fitted forests, device resident */
@@ -86,14 +87,15 @@ typedef struct {
  * column, repeats and values not below the column maximum dropped.  code(x) = the
  * number of thresholds strictly below x (-0.0 is treated as +0.0).
  * Errors: EINVAL for null pointers, n outside [1, AIWC_RF_MAX_ROWS], p outside
- * [1, 255], n_devices outside [1, 256], max_bins outside [2, 256], a NaN feature or
+ * [1, 254], n_devices outside [1, 256], max_bins outside [2, 256], a NaN feature or
  * a device id out of range; EINVAL also if an applied binner has another p.
  * Synchronous. */
 int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, int32_t n_devices,
                 int32_t max_bins, aiwc_rf_binner** binner, uint8_t* codes, void* stream);
 
-/* A binner that only carries bin counts (n_bins_host[n_cols], each in [1, 256]),
- * for fitting code matrices that were binned elsewhere.  It cannot bin features. */
+/* A binner that only carries bin counts (n_bins_host[n_cols], each in [1, 256];
+ * n_cols in [1, AIWC_RF_MAX_COLS]), for fitting code matrices that were binned
+ * elsewhere.  It cannot bin features. */
 int aiwc_rf_binner_from_counts(const int32_t* n_bins_host, int32_t n_cols, aiwc_rf_binner** binner);
 
 /* Copy out p, n_devices, the bin count of each of the p + 1 columns and the
@@ -101,6 +103,8 @@ int aiwc_rf_binner_from_counts(const int32_t* n_bins_host, int32_t n_cols, aiwc_
  * pointer may be NULL.  thresholds_host must be NULL for a counts-only binner. */
 int aiwc_rf_binner_export_host(const aiwc_rf_binner* binner, int32_t* p_host, int32_t* n_devices_host,
                                int32_t* n_bins_host, float* thresholds_host);
+/* Releases the binner.  Work enqueued on other streams that still reads its bin
+ * counts must be complete (synchronize those streams first). */
 void aiwc_rf_binner_free(aiwc_rf_binner* binner);
 
 /* ------------------------------------------------------------------------------
@@ -127,7 +131,8 @@ void aiwc_rf_binner_free(aiwc_rf_binner* binner);
 #define AIWC_RF_FIT_PLAIN 1u /* grid: one launch sequence per forest (same results) */
 #define AIWC_RF_FIT_ASYNC 2u /* return after enqueueing; aiwc_rf_forest_wait() reports the status */
 #define AIWC_RF_FIT_TUNE 4u  /* pick the workgroup shape by timing the candidates on an evenly
-                                strided sample of this call's trees (up to 64 per CU);
+                                strided sample of this call's trees (up to 64 per CU): workgroup
+                                size, wide limit, waves per SIMD and columns per large-node task;
                                 the choice is cached per problem shape (and in the file named by
                                 AIWC_RF_TUNE_CACHE, if set); results never depend on it.
                                 Without it the shape follows the problem size; the environment
@@ -162,14 +167,31 @@ int aiwc_rf_forest_wait(const aiwc_rf_forest* forest);
 int aiwc_rf_forest_info(const aiwc_rf_forest* forest, int32_t forest_index, int32_t* n_forests_host,
                         int32_t* n_cols_host, int32_t* num_trees_host, int64_t* total_nodes_host);
 
-/* Work statistics of a fit, for throughput accounting.  work_host[4] receives,
+/* Work statistics of a fit, for throughput accounting.  work_host[5] receives,
  * summed over the trees of forest forest_index: the in-bag rows of every node whose
  * split was searched, the number of such nodes, the in-bag rows of every node that
- * split (rows moved to children), and (max over trees) the number of levels grown.
+ * split (rows moved to children), (max over trees) the number of levels grown, and
+ * the rows added to LDS histogram bins (in-bag rows x mtry of every searched node
+ * above 32 rows: one LDS atomic add each).
  * grow_ms_host receives the device time of the call's tree-growing launch(es),
  * from events recorded on the fit stream around them (for a grid: the whole call).
  * Either output may be NULL.  Waits for an ASYNC fit. */
 int aiwc_rf_forest_stats(const aiwc_rf_forest* forest, int32_t forest_index, int64_t* work_host, float* grow_ms_host);
+
+/* The launch shape a fit used (the same for every forest of a grid).  Shapes never
+ * change results; this reports which one ran, for tests and profiles. */
+typedef struct {
+  int32_t block;          /* threads per workgroup of the grow kernel */
+  int32_t waves_per_simd; /* occupancy the grow kernel was compiled for */
+  int32_t wide_limit;     /* nodes with more in-bag rows are searched by the whole workgroup */
+  int32_t big_cols;       /* candidate columns per large-node task */
+  int32_t grid;           /* workgroups of the (largest) persistent grow launch */
+  int32_t wide_phase;     /* 1 when the kernel with the workgroup-wide phase ran */
+  int32_t graph;          /* 1 when the fit ran as one executable-graph launch (fused grid) */
+  int32_t graph_reused;   /* 1 when that graph was built by an earlier fit of the same shape */
+  int32_t tuned;          /* 1 when the shape came from the autotuner (timed now or cached) */
+} aiwc_rf_launch_info;
+int aiwc_rf_forest_launch(const aiwc_rf_forest* forest, aiwc_rf_launch_info* info_host);
 
 /* Node counts of trees [tree_begin, tree_end) of a forest (n_nodes_host[tree_end - tree_begin]). */
 int aiwc_rf_forest_tree_sizes(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
@@ -184,6 +206,9 @@ int aiwc_rf_forest_tree_sizes(const aiwc_rf_forest* forest, int32_t forest_index
 int aiwc_rf_forest_export_host(const aiwc_rf_forest* forest, int32_t forest_index, int32_t tree_begin,
                                int32_t tree_end, uint8_t* col_host, uint8_t* bin_host, int32_t* left_host,
                                int64_t* q_host, int32_t* N_host);
+/* Releases the forest.  Waits for the fit's own stream to finish the fit; work the
+ * caller enqueued on other streams that still reads the forest (predictions,
+ * scoring) must be complete first.  No other stream is waited for. */
 void aiwc_rf_forest_free(aiwc_rf_forest* forest);
 
 /* ------------------------------------------------------------------------------
@@ -307,24 +332,34 @@ int aiwc_rf_select_device(const aiwc_rf_forest* forest, int32_t forest_index, co
 
 /* ------------------------------------------------------------------------------
  * Serving (the scheduler-facing use of Sec. VI): a resident forest answers a
- * stream of prediction requests of different sizes.  Requests are admitted while
- * their staging memory fits the budget, packed into batches as they arrive
- * (continuous batching) and run on several streams so that copies and kernels of
- * different batches overlap.  Each answer equals what aiwc_rf_predict returns for
- * the same rows alone.
+ * stream of prediction requests of different sizes.  Requests are packed into
+ * batches as they arrive (continuous batching) and run on several streams, so that
+ * copies and kernels of different batches overlap.  Each answer equals what
+ * aiwc_rf_predict returns for the same rows alone.
  *
- * create:  forest/forest_index to serve; memory_budget_bytes caps the device and
- *          pinned staging held by admitted requests (each row costs n_cols + 8
- *          bytes); max_batch_rows caps one batch; n_streams in [1, 8].
+ * Memory admission: at creation the server allocates one device arena and one
+ * pinned host arena that together hold at most memory_budget_bytes, cut into row
+ * slots (a row costs 2 * n_cols + 24 bytes: n_cols + 16 on the device for its
+ * codes, sum and answer, n_cols + 8 pinned for its staged codes and answer).  A
+ * batch takes one contiguous range of slots and returns it when it completes;
+ * requests that arrive while no range is large enough wait, in arrival order,
+ * until running batches free their slots.  No allocation happens per request.
+ *
+ * create:  forest/forest_index to serve; memory_budget_bytes (see above);
+ *          max_batch_rows caps one batch; n_streams in [1, 8].  EINVAL for bad
+ *          arguments or a budget below one row, ESTATE if the fit failed, ENOMEM
+ *          if the arenas cannot be allocated.
  * submit:  codes_host is n x n_cols uint8, out_host receives n float64; both stay
  *          owned by the caller and must stay valid until the request completes.
  *          Never blocks; returns the request's ticket.  ENOMEM if n rows alone
- *          exceed the budget or max_batch_rows.
+ *          exceed the arenas or max_batch_rows; ESTATE once the server failed.
  * poll:    copies up to max_tickets completed tickets (completion order) and their
  *          latency in seconds (submit -> results in out_host); *n_done receives the
- *          count.
- * drain:   blocks until every submitted request has completed.
- * stats:   rows served, batches launched, peak admitted bytes. */
+ *          count.  EHIP (after copying) if a batch failed on the device.
+ * drain:   blocks until every submitted request has completed (EHIP on failure).
+ * stats:   rows served, batches launched, peak bytes of the arena slots in use,
+ *          and how many times the oldest waiting request had to wait for slots.
+ * Every failure sets aiwc_rf_last_error(). */
 typedef struct aiwc_rf_server aiwc_rf_server;
 int aiwc_rf_server_create(const aiwc_rf_forest* forest, int32_t forest_index, int64_t memory_budget_bytes,
                           int32_t max_batch_rows, int32_t n_streams, aiwc_rf_server** server);
@@ -334,7 +369,7 @@ int aiwc_rf_server_poll(aiwc_rf_server* server, int64_t* tickets_host, double* l
                         int32_t max_tickets, int32_t* n_done_host);
 int aiwc_rf_server_drain(aiwc_rf_server* server);
 int aiwc_rf_server_stats(const aiwc_rf_server* server, int64_t* rows_host, int64_t* batches_host,
-                         int64_t* peak_bytes_host);
+                         int64_t* peak_bytes_host, int64_t* memory_waits_host);
 void aiwc_rf_server_free(aiwc_rf_server* server);
 
 /* Message of the last failure on this thread ("" if none). */

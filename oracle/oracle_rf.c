@@ -38,6 +38,8 @@
 
 #define MAX_ROWS (1 << 18) /* fixed-point budget: |S| <= 2^40, Q <= 2^62 */
 #define LEAF_COL 255
+/* column ids must stay below the leaf marker: at most 255 code columns (254 features + device) */
+#define MAX_COLS 255
 
 /* ---------------------------------------------------------------------------
  * Philox4x64-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy
@@ -98,7 +100,7 @@ static int cmp_float(const void* a, const void* b) {
 }
 
 static int check_bin_args(const float* X, const int32_t* dev, int64_t n, int32_t p, int32_t n_devices) {
-  if (!X || !dev || n < 1 || n > MAX_ROWS || p < 1 || p > 255 || n_devices < 1 || n_devices > 256)
+  if (!X || !dev || n < 1 || n > MAX_ROWS || p < 1 || p > MAX_COLS - 1 || n_devices < 1 || n_devices > 256)
     return ORACLE_EINVAL;
   for (int64_t i = 0; i < n; i++) {
     if (dev[i] < 0 || dev[i] >= n_devices) return ORACLE_EINVAL;
@@ -359,7 +361,7 @@ int oracle_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const int32_t
                   int64_t capacity, uint8_t* col, uint8_t* bin, int32_t* left, int64_t* q,
                   int32_t* N, int64_t* n_nodes, int32_t n_threads) {
   if (!codes || !n_bins || !y || !prm || !col || !bin || !left || !q || !N || !n_nodes) return ORACLE_EINVAL;
-  if (n < 1 || n > MAX_ROWS || n_cols < 1 || n_cols > 256 || n_train < 1 || n_train > n) return ORACLE_EINVAL;
+  if (n < 1 || n > MAX_ROWS || n_cols < 1 || n_cols > MAX_COLS || n_train < 1 || n_train > n) return ORACLE_EINVAL;
   if (prm->num_trees < 1 || prm->num_trees > (1 << 14) || prm->mtry < 1 || prm->mtry > n_cols ||
       prm->min_node_size < 1 || tree_begin < 0 || tree_end > prm->num_trees || tree_begin >= tree_end)
     return ORACLE_EINVAL;

@@ -7,7 +7,7 @@ Submodules are imported lazily so that the pure-NumPy generator can be used
 without touching the GPU library.
 """
 
-__all__ = ["synth", "rf", "grid", "serve", "autotune"]
+__all__ = ["synth", "rf"]
 
 
 def __getattr__(name):

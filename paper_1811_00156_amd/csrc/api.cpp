@@ -16,26 +16,6 @@ using namespace aiwc;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-template <typename F>
-int guard(F&& f) {
-  try {
-    f();
-    g_last_error.clear();
-    return AIWC_RF_OK;
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return AIWC_RF_ENOMEM;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return AIWC_RF_EINVAL;
-  }
-}
-
 void require(bool ok, const char* what) {
   if (!ok) fail(AIWC_RF_EINVAL, what);
 }
@@ -179,9 +159,9 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
     for (int rep = 0; rep < 2; ++rep) {
       launch_init(nullptr, queue, s);
       AIWC_HIP(hipEventRecord(e0, s));
-      launch_grow(c, codes, codes_p, n_cols, binner->d_n_bins.p, y_fp, d_train, d_trial, (int32_t)trial,
-                  F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue, F->status.p, scratch.p,
-                  base.n_cap, mtry_max, grid, s);
+      const GrowLaunch g{codes, codes_p, d_train, d_trial, (int32_t)trial, F->nodes.p, F->node_N.p,
+                         F->n_nodes.p, F->work.p, F->inbag.p, queue, scratch.p, base.n_cap};
+      launch_grow(c, g, n_cols, binner->d_n_bins.p, y_fp, F->status.p, mtry_max, grid, s);
       AIWC_HIP(hipEventRecord(e1, s));
       AIWC_HIP(hipEventSynchronize(e1));
       float m = 0.0f;
@@ -211,14 +191,12 @@ void require_fitted(const aiwc_rf_forest* f) {
 
 extern "C" {
 
-const char* aiwc_rf_last_error(void) { return g_last_error.c_str(); }
-
 int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, int32_t n_devices, int32_t max_bins,
                 aiwc_rf_binner** binner, uint8_t* codes, void* stream) {
   return guard([&] {
     require(X && device_id && codes && binner, "null pointer argument");
     require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
-    require(p >= 1 && p <= AIWC_RF_MAX_FEATURES, "p must be in [1, 255]");
+    require(p >= 1 && p <= AIWC_RF_MAX_FEATURES, "p must be in [1, 254]");
     require(n_devices >= 1 && n_devices <= 256, "n_devices must be in [1, 256]");
     hipStream_t s = as_stream(stream);
     const bool fit = *binner == nullptr;
@@ -264,7 +242,7 @@ int aiwc_rf_bin(const float* X, const int32_t* device_id, int64_t n, int32_t p, 
 int aiwc_rf_binner_from_counts(const int32_t* n_bins_host, int32_t n_cols, aiwc_rf_binner** binner) {
   return guard([&] {
     require(n_bins_host && binner, "null pointer argument");
-    require(n_cols >= 1 && n_cols <= 256, "n_cols must be in [1, 256]");
+    require(n_cols >= 1 && n_cols <= AIWC_RF_MAX_COLS, "n_cols must be in [1, 255]");
     for (int32_t c = 0; c < n_cols; ++c) require(n_bins_host[c] >= 1 && n_bins_host[c] <= 256, "bin count outside [1, 256]");
     std::unique_ptr<aiwc_rf_binner> b(new aiwc_rf_binner());
     AIWC_HIP(hipGetDevice(&b->device));
@@ -293,8 +271,8 @@ int aiwc_rf_binner_export_host(const aiwc_rf_binner* b, int32_t* p_host, int32_t
 }
 
 void aiwc_rf_binner_free(aiwc_rf_binner* b) {
-  if (!b) return;
-  (void)hipDeviceSynchronize();
+  // every call that fills a binner's arrays has completed when it returns;
+  // its device arrays go back to the cache behind the streams that used them
   delete b;
 }
 
@@ -331,7 +309,7 @@ void check_fit_args(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_
                     aiwc_rf_forest** forest) {
   require(codes && binner && y_log10 && params_host && forest, "null pointer argument");
   require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
-  require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
+  require(n_cols >= 1 && n_cols <= AIWC_RF_MAX_COLS && (size_t)n_cols == binner->n_bins.size(),
           "n_cols must equal the binner's column count");
   require(n_forests >= 1, "n_forests must be >= 1");
   require((flags & ~(AIWC_RF_FIT_PLAIN | AIWC_RF_FIT_ASYNC | AIWC_RF_FIT_TUNE)) == 0, "unknown flag");
@@ -401,7 +379,7 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   F->nodes.reset((size_t)pool, s);
   F->node_N.reset((size_t)pool, s);
   F->n_nodes.reset((size_t)n_tasks, s);
-  F->work.reset((size_t)n_tasks * 4, s);
+  F->work.reset((size_t)n_tasks * kWorkWords, s);
   F->node_base.reset((size_t)n_tasks, s);
   F->status.reset(1, s);
   F->status_host = pinned_word_acquire();
@@ -432,8 +410,18 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
   const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
   const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
-  if (flags & AIWC_RF_FIT_TUNE) cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p,
-                                                d_train.p, queue.p, s);
+  bool tuned = false;
+  if (flags & AIWC_RF_FIT_TUNE) {
+    cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p, d_train.p, queue.p, s);
+    tuned = true;
+  }
+  aiwc_rf_launch_info& LI = F->launch;
+  LI.block = cfg.block;
+  LI.waves_per_simd = grow_has_wide_phase(cfg) ? 4 : cfg.occupancy;
+  LI.wide_limit = cfg.huge_min;
+  LI.big_cols = effective_big_cols(cfg, mtry_max, n_cols);
+  LI.wide_phase = grow_has_wide_phase(cfg) ? 1 : 0;
+  LI.tuned = tuned ? 1 : 0;
 
   if (plain) {
     // one launch sequence per forest, as separate fits would issue them
@@ -441,62 +429,40 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     DevBuf<uint8_t> scratch(per_wg * (size_t)grid_max, s);
     launch_init(F->status.p, nullptr, s);
     AIWC_HIP(hipEventRecord(F->grow_begin, s));
+    int grid_used = 0;
     for (int32_t f = 0; f < n_forests; ++f) {
       const int64_t t0 = F->first_task[f];
       const int32_t nt = params_host[f].num_trees;
       const int grid = grow_grid_size(cfg, nt, mtry_max, n_cols);
+      grid_used = std::max(grid_used, grid);
       launch_init(nullptr, queue.p, s);
       launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
-      launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p + t0, nt,
-                  F->nodes.p, F->node_N.p, F->n_nodes.p + t0, F->work.p + 4 * t0, F->inbag.p, queue.p, F->status.p, scratch.p,
-                  n_cap, mtry_max, grid, s);
+      const GrowLaunch g{codes, codes_p.p, d_train.p, F->d_tasks.p + t0, nt, F->nodes.p, F->node_N.p,
+                         F->n_nodes.p + t0, F->work.p + kWorkWords * t0, F->inbag.p, queue.p, scratch.p, n_cap};
+      launch_grow(cfg, g, n_cols, binner->d_n_bins.p, y_fp.p, F->status.p, mtry_max, grid, s);
     }
     AIWC_HIP(hipEventRecord(F->grow_end, s));
+    LI.grid = grid_used;
   } else {
     const int grid = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
+    LI.grid = grid;
     DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
+    const GrowLaunch g{codes, codes_p.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks, F->nodes.p, F->node_N.p,
+                       F->n_nodes.p, F->work.p, F->inbag.p, queue.p, scratch.p, n_cap};
     if (n_forests > 1) {
-      // fused grid: the whole fit as one captured graph
-      hipStream_t cs;
-      AIWC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      hipEvent_t ev;
-      AIWC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      AIWC_HIP(hipEventRecord(ev, s));
-      AIWC_HIP(hipStreamWaitEvent(cs, ev, 0));
-      hipGraph_t graph = nullptr;
-      hipGraphExec_t exec = nullptr;
-      AIWC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      try {
-        launch_init(F->status.p, queue.p, cs);
-        launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, cs);
-        launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                    F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap,
-                    mtry_max, grid, cs);
-      } catch (...) {
-        (void)hipStreamEndCapture(cs, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipStreamDestroy(cs);
-        (void)hipEventDestroy(ev);
-        throw;
-      }
-      AIWC_HIP(hipStreamEndCapture(cs, &graph));
-      AIWC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-      // timing events bracket the whole graph (initialise, prepare, grow)
+      // fused grid: the whole fit as one executable-graph launch (timing events
+      // bracket the whole graph: reset, prepare, grow)
       AIWC_HIP(hipEventRecord(F->grow_begin, s));
-      AIWC_HIP(hipGraphLaunch(exec, s));
+      const bool reused = launch_fit_graph(cfg, g, codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, F->status.p,
+                                           mtry_max, grid, s);
       AIWC_HIP(hipEventRecord(F->grow_end, s));
-      AIWC_HIP(hipStreamSynchronize(s));
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
-      (void)hipStreamDestroy(cs);
-      (void)hipEventDestroy(ev);
+      LI.graph = 1;
+      LI.graph_reused = reused ? 1 : 0;
     } else {
       launch_init(F->status.p, queue.p, s);
       launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y_log10, y_fp.p, codes_p.p, F->status.p, s);
       AIWC_HIP(hipEventRecord(F->grow_begin, s));
-      launch_grow(cfg, codes, codes_p.p, n_cols, binner->d_n_bins.p, y_fp.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks,
-                  F->nodes.p, F->node_N.p, F->n_nodes.p, F->work.p, F->inbag.p, queue.p, F->status.p, scratch.p, n_cap, mtry_max,
-                  grid, s);
+      launch_grow(cfg, g, n_cols, binner->d_n_bins.p, y_fp.p, F->status.p, mtry_max, grid, s);
       AIWC_HIP(hipEventRecord(F->grow_end, s));
     }
   }
@@ -594,7 +560,7 @@ int aiwc_rf_forest_wait(const aiwc_rf_forest* f) {
     code = resolve_status(f, msg);
   });
   if (rc != AIWC_RF_OK) return rc;
-  if (code != AIWC_RF_OK) g_last_error = msg;
+  if (code != AIWC_RF_OK) set_last_error(msg);
   return code;
 }
 
@@ -628,16 +594,23 @@ int aiwc_rf_forest_stats(const aiwc_rf_forest* f, int32_t forest_index, int64_t*
     if (code != AIWC_RF_OK) fail(AIWC_RF_ESTATE, "fit failed: " + msg);
     if (work_host) {
       const int32_t nt = f->params[forest_index].num_trees;
-      std::vector<int64_t> w((size_t)nt * 4);
-      AIWC_HIP(hipMemcpy(w.data(), f->work.p + 4 * f->first_task[forest_index], sizeof(int64_t) * w.size(),
+      std::vector<int64_t> w((size_t)nt * kWorkWords);
+      AIWC_HIP(hipMemcpy(w.data(), f->work.p + kWorkWords * f->first_task[forest_index], sizeof(int64_t) * w.size(),
                          hipMemcpyDeviceToHost));
-      for (int i = 0; i < 4; ++i) work_host[i] = 0;
+      for (int i = 0; i < kWorkWords; ++i) work_host[i] = 0;
       for (int32_t t = 0; t < nt; ++t) {
-        for (int i = 0; i < 3; ++i) work_host[i] += w[4 * t + i];
-        work_host[3] = std::max(work_host[3], w[4 * t + 3]);
+        for (int i = 0; i < kWorkWords; ++i)
+          work_host[i] = i == 3 ? std::max(work_host[i], w[kWorkWords * t + i]) : work_host[i] + w[kWorkWords * t + i];
       }
     }
     if (grow_ms_host) AIWC_HIP(hipEventElapsedTime(grow_ms_host, f->grow_begin, f->grow_end));
+  });
+}
+
+int aiwc_rf_forest_launch(const aiwc_rf_forest* f, aiwc_rf_launch_info* info_host) {
+  return guard([&] {
+    require(f != nullptr && info_host != nullptr, "null pointer argument");
+    *info_host = f->launch;
   });
 }
 
@@ -691,7 +664,9 @@ int aiwc_rf_forest_export_host(const aiwc_rf_forest* f, int32_t forest_index, in
 
 void aiwc_rf_forest_free(aiwc_rf_forest* f) {
   if (!f) return;
-  (void)hipDeviceSynchronize();
+  // only the fit's own stream is waited for (its status word is copied there);
+  // work the caller enqueued on other streams must be complete (header)
+  if (f->done) (void)hipEventSynchronize(f->done);
   if (f->done) (void)hipEventDestroy(f->done);
   if (f->grow_begin) (void)hipEventDestroy(f->grow_begin);
   if (f->grow_end) (void)hipEventDestroy(f->grow_end);
@@ -830,7 +805,7 @@ int aiwc_rf_tune_sa(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_
   return guard([&] {
     require(codes && binner && y_log10 && cfg && best_params_host && best_objective_host, "null pointer argument");
     require(n >= 1 && n <= AIWC_RF_MAX_ROWS, "n must be in [1, 2^18]");
-    require(n_cols >= 1 && n_cols <= 256 && (size_t)n_cols == binner->n_bins.size(),
+    require(n_cols >= 1 && n_cols <= AIWC_RF_MAX_COLS && (size_t)n_cols == binner->n_bins.size(),
             "n_cols must equal the binner's column count");
     anneal(codes, n, n_cols, binner, y_log10, *cfg, best_params_host, best_objective_host, trace_host,
            as_stream(stream));

@@ -30,6 +30,11 @@
 // the order in which rows are visited never changes a result.
 #include <limits.h>
 
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device.h"
 #include "internal.h"
 
@@ -176,7 +181,7 @@ struct GrowArgs {
   uint64_t* nodes;
   uint32_t* node_N;
   int32_t* n_nodes;
-  int64_t* work;  // per task: searched rows, searched nodes, partitioned rows, levels
+  int64_t* work;  // per task (kWorkWords each): searched rows, searched nodes, partitioned rows, levels, LDS bin adds
   uint64_t* inbag;
   uint32_t* queue;
   uint32_t* status;
@@ -982,7 +987,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
   const int64_t base_node = T.node_base;
   uint32_t level_lo = 0, level_cnt = 1, next_id = 1;
   int cur = 0;
-  uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0;
+  uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0, work_hist = 0;
   while (level_cnt > 0) {
     ++levels;
     const Level2 C = cur ? sc.L1 : sc.L0;  // this level
@@ -1003,6 +1008,8 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
         }
         work_rows += len;
         ++work_nodes;
+        // nodes above 32 rows add each row to an LDS bin per candidate column
+        if (len > 32) work_hist += (uint64_t)len * (uint64_t)mtry;
         uint32_t* bt = nullptr;
         if (len <= kSegMax) {
           const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
@@ -1192,13 +1199,15 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
   work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
   work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, sh.red);
   work_part = block_sum<BLOCK, uint64_t>(work_part, sh.red);
+  work_hist = block_sum<BLOCK, uint64_t>(work_hist, sh.red);
   if (tid == 0) {
     a.n_nodes[task_index] = (int32_t)next_id;
-    int64_t* wk = a.work + 4 * (int64_t)task_index;
+    int64_t* wk = a.work + kWorkWords * (int64_t)task_index;
     wk[0] = (int64_t)work_rows;
     wk[1] = (int64_t)work_nodes;
     wk[2] = (int64_t)work_part;
     wk[3] = (int64_t)levels;
+    wk[4] = (int64_t)work_hist;
   }
   (void)wid;
 }
@@ -1210,6 +1219,10 @@ template <int BLOCK, bool WIDE, int OCC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) void k_grow(GrowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ Shared sh;
+  // a code at or above its column's bin count (flagged by the prepare kernel,
+  // which ran before on this stream) would index past a histogram: grow nothing
+  // and let the fit report EINVAL
+  if (__atomic_load_n(a.status, __ATOMIC_RELAXED) & kStatusBadCode) return;
   Scratch sc;
   carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max);
   for (int c = threadIdx.x; c < a.C; c += BLOCK) sh.nbins[c] = (uint16_t)a.n_bins[c];
@@ -1275,9 +1288,6 @@ struct Layout {
   int32_t big_cols;    // large-node columns per wave task (the wave area holds that many histograms)
 };
 
-// A launch has wide nodes iff a tree's training set exceeds the wide limit.
-bool wide_launch(const GrowConfig& cfg) { return cfg.n_cap > cfg.huge_min; }
-
 Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   Layout L;
   L.bstride = (std::max(cfg.bins_max, 1) + 63) / 64 * 64;
@@ -1290,7 +1300,7 @@ Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   const size_t waves = (size_t)(cfg.block / kWave) * L.wave_bytes;
   const size_t draw = (size_t)std::min(cfg.block, 256) * (size_t)C;
   size_t wide = 0;
-  if (wide_launch(cfg)) {
+  if (grow_has_wide_phase(cfg)) {
     // by default a quarter of the 128 KiB per 256 threads, so that the
     // workgroups that fit a CU still do
     const size_t want = cfg.wide_bytes > 0 ? (size_t)cfg.wide_bytes : (size_t)cfg.block * 128;
@@ -1348,61 +1358,185 @@ size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max) {
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
                     int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s) {
   const int64_t work = n * padded_cols(C);
-  const int blocks = (int)std::min<int64_t>(2048, (work + 255) / 256);
-  k_prepare<<<std::max(blocks, 1), 256, 0, s>>>(codes, n, C, d_n_bins, y, y_fp, codes_p, padded_cols(C), d_status);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (work + 255) / 256));
+  k_prepare<<<blocks, 256, 0, s>>>(codes, n, C, d_n_bins, y, y_fp, codes_p, padded_cols(C), d_status);
   AIWC_HIP(hipGetLastError());
 }
 
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C) {
   const uint32_t lds = grow_layout(cfg, mtry_max, C).union_bytes;
   if (lds > device_info().lds_per_block) fail(AIWC_RF_EINVAL, "grow kernel LDS exceeds the device limit");
-  int per_cu = occupancy(grow_kernel_for(cfg, wide_launch(cfg)), cfg.block, lds);
+  int per_cu = occupancy(grow_kernel_for(cfg, grow_has_wide_phase(cfg)), cfg.block, lds);
   if (per_cu < 1) fail(AIWC_RF_ENOMEM, "grow kernel does not fit the device (LDS or registers)");
   if (cfg.wg_per_cu > 0) per_cu = std::min(per_cu, cfg.wg_per_cu);
   const int64_t slots = (int64_t)device_info().cus * per_cu;
   return (int)std::max<int64_t>(1, std::min<int64_t>(slots, n_tasks));
 }
 
-void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* codes_p, int32_t C, const int32_t* d_n_bins,
-                 const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
-                 uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,
-                 hipStream_t s) {
+namespace {
+
+GrowArgs grow_args(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const int32_t* d_n_bins, const int64_t* y_fp,
+                   uint32_t* d_status, int32_t mtry_max) {
   GrowArgs a;
-  a.codes = codes;
+  a.codes = g.codes;
   a.C = C;
-  a.codes_p = codes_p;
+  a.codes_p = g.codes_p;
   a.Cp = padded_cols(C);
-  const bool dense = n_cap * (int64_t)C <= (int64_t)1 << 20;
-  a.rcodes = dense ? codes : codes_p;
+  const bool dense = g.n_cap * (int64_t)C <= (int64_t)1 << 20;
+  a.rcodes = dense ? g.codes : g.codes_p;
   a.rC = dense ? C : a.Cp;
   a.n_bins = d_n_bins;
   a.y_fp = y_fp;
-  a.train_rows = train_rows;
-  a.tasks = d_tasks;
-  a.n_tasks = n_tasks;
-  a.nodes = nodes;
-  a.node_N = node_N;
-  a.n_nodes = n_nodes;
-  a.work = work;
-  a.inbag = inbag;
-  a.queue = d_queue;
+  a.train_rows = g.train_rows;
+  a.tasks = g.tasks;
+  a.n_tasks = g.n_tasks;
+  a.nodes = g.nodes;
+  a.node_N = g.node_N;
+  a.n_nodes = g.n_nodes;
+  a.work = g.work;
+  a.inbag = g.inbag;
+  a.queue = g.queue;
   a.status = d_status;
-  a.scratch = scratch;
-  a.n_cap = n_cap;
+  a.scratch = g.scratch;
+  a.n_cap = g.n_cap;
   a.mtry_max = mtry_max;
   a.huge_min = cfg.huge_min;
-  a.scratch_stride = grow_scratch_bytes(n_cap, mtry_max);
+  a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max);
   const Layout L = grow_layout(cfg, mtry_max, C);
   a.union_bytes = L.union_bytes;
   a.wave_bytes = L.wave_bytes;
   a.bstride = L.bstride;
   a.big_stride = L.big_stride;
   a.big_cols = cfg.big_cols > 0 ? std::min(cfg.big_cols, L.big_cols) : L.big_cols;
-  const void* kernel = grow_kernel_for(cfg, wide_launch(cfg));
+  return a;
+}
+
+int prepare_blocks(int64_t n, int32_t C) {
+  const int64_t work = n * padded_cols(C);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (work + 255) / 256));
+}
+
+// Executable graphs of fused fits, one per launch shape: the status and queue
+// reset, the prepare kernel and the grow launch as three kernel nodes.  A later
+// fit of the same shape only replaces the nodes' arguments, once the graph's
+// previous launch has finished.
+struct GraphKey {
+  int device;
+  const void* kernel;
+  int block, grid, prep_blocks;
+  uint32_t lds;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(device, kernel, block, grid, prep_blocks, lds) <
+           std::tie(o.device, o.kernel, o.block, o.grid, o.prep_blocks, o.lds);
+  }
+};
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t init = nullptr, prep = nullptr, grow = nullptr;
+  hipEvent_t last = nullptr;  // recorded after the latest launch
+  uint64_t used = 0;
+};
+constexpr size_t kMaxGraphs = 16;
+
+std::mutex& graph_mu() {
+  static std::mutex* m = new std::mutex();
+  return *m;
+}
+std::map<GraphKey, GraphEntry>& graph_cache() {
+  static auto* c = new std::map<GraphKey, GraphEntry>();  // kept until exit
+  return *c;
+}
+
+hipKernelNodeParams node_params(const void* fn, int grid, int block, uint32_t lds, void** args) {
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.func = const_cast<void*>(fn);
+  p.gridDim = dim3((unsigned)grid);
+  p.blockDim = dim3((unsigned)block);
+  p.sharedMemBytes = lds;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+
+}  // namespace
+
+int effective_big_cols(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
+  const Layout L = grow_layout(cfg, mtry_max, C);
+  return cfg.big_cols > 0 ? std::min(cfg.big_cols, L.big_cols) : L.big_cols;
+}
+
+void launch_grow(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const int32_t* d_n_bins, const int64_t* y_fp,
+                 uint32_t* d_status, int32_t mtry_max, int grid, hipStream_t s) {
+  GrowArgs a = grow_args(cfg, g, C, d_n_bins, y_fp, d_status, mtry_max);
+  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg));
   void* args[] = {&a};
   AIWC_HIP(hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, a.union_bytes, s));
   AIWC_HIP(hipGetLastError());
+}
+
+bool launch_fit_graph(const GrowConfig& cfg, const GrowLaunch& g, const uint8_t* codes, int64_t n, int32_t C,
+                      const int32_t* d_n_bins, const double* y, int64_t* y_fp, uint32_t* d_status, int32_t mtry_max,
+                      int grid, hipStream_t s) {
+  GrowArgs a = grow_args(cfg, g, C, d_n_bins, y_fp, d_status, mtry_max);
+  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg));
+  const int pb = prepare_blocks(n, C);
+  int32_t Cp = padded_cols(C);
+  uint32_t* queue = g.queue;
+  uint8_t* codes_p = g.codes_p;
+  void* init_args[] = {&d_status, &queue};
+  void* prep_args[] = {const_cast<uint8_t**>(&codes), &n, &C, const_cast<int32_t**>(&d_n_bins),
+                       const_cast<double**>(&y), &y_fp, &codes_p, &Cp, &d_status};
+  void* grow_args_v[] = {&a};
+  const hipKernelNodeParams p_init = node_params(reinterpret_cast<const void*>(k_init), 1, 64, 0, init_args);
+  const hipKernelNodeParams p_prep = node_params(reinterpret_cast<const void*>(k_prepare), pb, 256, 0, prep_args);
+  const hipKernelNodeParams p_grow = node_params(kernel, grid, cfg.block, a.union_bytes, grow_args_v);
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  const GraphKey key{dev, kernel, cfg.block, grid, pb, a.union_bytes};
+  static uint64_t clock = 0;
+  std::lock_guard<std::mutex> lk(graph_mu());
+  auto& cache = graph_cache();
+  auto it = cache.find(key);
+  const bool reused = it != cache.end();
+  if (reused) {
+    GraphEntry& e = it->second;
+    AIWC_HIP(hipEventSynchronize(e.last));  // its previous launch read the old arguments
+    AIWC_HIP(hipGraphExecKernelNodeSetParams(e.exec, e.init, &p_init));
+    AIWC_HIP(hipGraphExecKernelNodeSetParams(e.exec, e.prep, &p_prep));
+    AIWC_HIP(hipGraphExecKernelNodeSetParams(e.exec, e.grow, &p_grow));
+  } else {
+    if (cache.size() >= kMaxGraphs) {  // drop the least recently used shape
+      auto old = cache.begin();
+      for (auto j = cache.begin(); j != cache.end(); ++j)
+        if (j->second.used < old->second.used) old = j;
+      (void)hipEventSynchronize(old->second.last);
+      (void)hipGraphExecDestroy(old->second.exec);
+      (void)hipGraphDestroy(old->second.graph);
+      (void)hipEventDestroy(old->second.last);
+      cache.erase(old);
+    }
+    GraphEntry e;
+    try {
+      AIWC_HIP(hipGraphCreate(&e.graph, 0));
+      AIWC_HIP(hipGraphAddKernelNode(&e.init, e.graph, nullptr, 0, &p_init));
+      AIWC_HIP(hipGraphAddKernelNode(&e.prep, e.graph, &e.init, 1, &p_prep));
+      AIWC_HIP(hipGraphAddKernelNode(&e.grow, e.graph, &e.prep, 1, &p_grow));
+      AIWC_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+      AIWC_HIP(hipEventCreateWithFlags(&e.last, hipEventDisableTiming));
+    } catch (...) {
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+      if (e.graph) (void)hipGraphDestroy(e.graph);
+      throw;
+    }
+    it = cache.emplace(key, e).first;
+  }
+  GraphEntry& e = it->second;
+  e.used = ++clock;
+  AIWC_HIP(hipGraphLaunch(e.exec, s));
+  AIWC_HIP(hipEventRecord(e.last, s));
+  return reused;
 }
 
 }  // namespace aiwc

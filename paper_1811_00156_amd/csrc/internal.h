@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -23,6 +25,29 @@ struct Error {
 [[noreturn]] void fail(int code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 #define AIWC_HIP(call) ::aiwc::hip_check((call), #call)
+
+// The calling thread's last error message (what aiwc_rf_last_error returns).
+void set_last_error(const std::string& msg);
+
+// Runs f, converting what it throws into a return code and the thread's
+// message; a call that succeeds clears the message.
+template <typename F>
+int guard(F&& f) {
+  try {
+    f();
+    set_last_error(std::string());
+    return AIWC_RF_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return AIWC_RF_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return AIWC_RF_EINVAL;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Device memory cache.  Blocks are rounded up to 1 MiB multiples (small blocks
@@ -126,6 +151,11 @@ struct TreeTask {
   int64_t inbag_off;  // first 64-bit word of the tree's in-bag bitmap over its training rows, -1 = none
 };
 
+// Work counters a fit writes per tree: searched rows, searched nodes,
+// partitioned rows, levels, and rows added to LDS histogram bins (one per
+// candidate column of every node above 32 rows).
+constexpr int kWorkWords = 5;
+
 // Status bits a fit raises on the device.
 constexpr uint32_t kStatusBadY = 1u;
 constexpr uint32_t kStatusBadCode = 2u;
@@ -145,7 +175,7 @@ struct aiwc_rf_forest {
   aiwc::DevBuf<uint64_t> nodes;            // node words, all slots
   aiwc::DevBuf<uint32_t> node_N;           // bootstrap weight per node
   aiwc::DevBuf<int32_t> n_nodes;           // per task
-  aiwc::DevBuf<int64_t> work;              // per task: searched rows, searched nodes, partitioned rows, levels
+  aiwc::DevBuf<int64_t> work;              // per task: kWorkWords counters
   aiwc::DevBuf<int64_t> node_base;         // per task, device copy for traversal
   aiwc::DevBuf<uint32_t> status;           // device status word
   uint32_t* status_host = nullptr;         // pinned
@@ -155,6 +185,7 @@ struct aiwc_rf_forest {
   int32_t fit_status = 0;                  // resolved status after wait
   bool waited = false;
   int64_t pool_nodes = 0;
+  aiwc_rf_launch_info launch{};            // the launch shape the fit used
   std::vector<int32_t> n_bins;             // bin count of every code column (device column last)
   aiwc::DevBuf<int32_t> train_rows;        // training-row lists of the forests that hold out a fold
   aiwc::DevBuf<uint64_t> inbag;            // per tree: bit i set if training row i is in its bootstrap sample
@@ -200,6 +231,10 @@ struct TuneKey {
   int mtry_max;
   int tasks_log2;
 };
+// A launch needs the kernel with the workgroup-wide phase iff a tree's
+// training set exceeds the wide limit.
+inline bool grow_has_wide_phase(const GrowConfig& cfg) { return cfg.n_cap > cfg.huge_min; }
+
 bool tune_lookup(const TuneKey& key, GrowConfig* cfg);
 void tune_store(const TuneKey& key, const GrowConfig& cfg);
 std::vector<GrowConfig> tune_candidates(const GrowConfig& base);
@@ -224,11 +259,33 @@ void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d
                     int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s);
 size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
-void launch_grow(const GrowConfig& cfg, const uint8_t* codes, const uint8_t* codes_p, int32_t C, const int32_t* d_n_bins,
-                 const int64_t* y_fp, const int32_t* train_rows, const TreeTask* d_tasks, int32_t n_tasks,
-                 uint64_t* nodes, uint32_t* node_N, int32_t* n_nodes, int64_t* work, uint64_t* inbag,
-                 uint32_t* d_queue, uint32_t* d_status, uint8_t* scratch, int64_t n_cap, int32_t mtry_max, int grid,
-                 hipStream_t s);
+// The buffers of one grow launch: the codes (dense and row-padded), the
+// training-row lists, the tasks and everything the trees write.
+struct GrowLaunch {
+  const uint8_t* codes;
+  uint8_t* codes_p;
+  const int32_t* train_rows;
+  const TreeTask* tasks;
+  int32_t n_tasks;
+  uint64_t* nodes;
+  uint32_t* node_N;
+  int32_t* n_nodes;
+  int64_t* work;
+  uint64_t* inbag;
+  uint32_t* queue;
+  uint8_t* scratch;
+  int64_t n_cap;
+};
+void launch_grow(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const int32_t* d_n_bins, const int64_t* y_fp,
+                 uint32_t* d_status, int32_t mtry_max, int grid, hipStream_t s);
+// Columns per large-node task that a launch shape actually uses.
+int effective_big_cols(const GrowConfig& cfg, int32_t mtry_max, int32_t C);
+// A fused fit as one executable graph launch (status and queue reset, prepare,
+// grow), cached per launch shape: returns true when the graph of an earlier
+// call was re-launched with this call's arguments instead of being built.
+bool launch_fit_graph(const GrowConfig& cfg, const GrowLaunch& g, const uint8_t* codes, int64_t n, int32_t C,
+                      const int32_t* d_n_bins, const double* y, int64_t* y_fp, uint32_t* d_status, int32_t mtry_max,
+                      int grid, hipStream_t s);
 
 // oob.hip: out-of-bag sums of every training row of forests [f0, f1), then
 // the squared and absolute errors of the out-of-bag predictions per forest.

@@ -16,6 +16,12 @@ namespace aiwc {
 
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 void hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return;
   if (e == hipErrorOutOfMemory) {
@@ -281,7 +287,7 @@ std::string key_text(const TuneKey& k) {
 struct TuneCache {
   std::mutex mu;
   bool loaded = false;
-  std::map<std::string, std::array<int, 3>> entries;  // key -> (block, huge_min, occupancy)
+  std::map<std::string, std::array<int, 4>> entries;  // key -> (block, huge_min, occupancy, big_cols)
 };
 
 TuneCache& tune_cache() {
@@ -298,13 +304,14 @@ void load_file_locked(TuneCache& c) {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    // "<key> | block=<b> huge_min=<h> occupancy=<o>"
+    // "<key> | block=<b> huge_min=<h> occupancy=<o> big_cols=<c>"
     char* bar = std::strchr(line, '|');
     if (!bar) continue;
     std::string key(line, bar - line);
     while (!key.empty() && key.back() == ' ') key.pop_back();
-    int b = 0, h = 0, o = 0;
-    if (std::sscanf(bar + 1, " block=%d huge_min=%d occupancy=%d", &b, &h, &o) == 3) c.entries[key] = {b, h, o};
+    int b = 0, h = 0, o = 0, g = 0;
+    if (std::sscanf(bar + 1, " block=%d huge_min=%d occupancy=%d big_cols=%d", &b, &h, &o, &g) == 4)
+      c.entries[key] = {b, h, o, g};
   }
   std::fclose(f);
 }
@@ -320,6 +327,7 @@ bool tune_lookup(const TuneKey& key, GrowConfig* cfg) {
   cfg->block = it->second[0];
   cfg->huge_min = it->second[1];
   cfg->occupancy = it->second[2];
+  cfg->big_cols = it->second[3];
   return true;
 }
 
@@ -328,10 +336,11 @@ void tune_store(const TuneKey& key, const GrowConfig& cfg) {
   std::lock_guard<std::mutex> g(c.mu);
   load_file_locked(c);
   const std::string k = key_text(key);
-  c.entries[k] = {cfg.block, cfg.huge_min, cfg.occupancy};
+  c.entries[k] = {cfg.block, cfg.huge_min, cfg.occupancy, cfg.big_cols};
   if (const char* path = std::getenv("AIWC_RF_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s | block=%d huge_min=%d occupancy=%d\n", k.c_str(), cfg.block, cfg.huge_min, cfg.occupancy);
+      std::fprintf(f, "%s | block=%d huge_min=%d occupancy=%d big_cols=%d\n", k.c_str(), cfg.block, cfg.huge_min,
+                   cfg.occupancy, cfg.big_cols);
       std::fclose(f);
     }
   }
@@ -340,7 +349,8 @@ void tune_store(const TuneKey& key, const GrowConfig& cfg) {
 std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
   // workgroup size x wide-node limit; a limit at or above the largest training
   // set means no wide nodes, timed once per workgroup size at 4, 5 and 6 waves
-  // per SIMD
+  // per SIMD.  Where large-node tasks exist (limit above 64 rows) each shape is
+  // timed with two and with four candidate columns per task.
   std::vector<GrowConfig> out;
   for (int block : {192, 256, 512, 1024}) {
     bool narrow_done = false;
@@ -350,11 +360,15 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
       narrow_done = narrow_done || narrow;
       for (int occ : {4, 5, 6}) {
         if (!narrow && occ != 4) continue;
-        GrowConfig c = base;
-        c.block = block;
-        c.huge_min = h;
-        c.occupancy = occ;
-        out.push_back(c);
+        for (int bc : {2, 4}) {
+          if (h <= 64 && bc != 2) continue;  // no large-node tasks: one timing suffices
+          GrowConfig c = base;
+          c.block = block;
+          c.huge_min = h;
+          c.occupancy = occ;
+          c.big_cols = bc;
+          out.push_back(c);
+        }
       }
     }
   }
@@ -362,3 +376,5 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
 }
 
 }  // namespace aiwc
+
+extern "C" const char* aiwc_rf_last_error(void) { return aiwc::g_last_error.c_str(); }

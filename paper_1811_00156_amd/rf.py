@@ -57,6 +57,7 @@ _sig("aiwc_rf_forest_wait", [_P])
 _sig("aiwc_rf_forest_info", [_P, _i32, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_tree_sizes", [_P, _i32, _i32, _i32, _P])
 _sig("aiwc_rf_forest_stats", [_P, _i32, _P, _P])
+_sig("aiwc_rf_forest_launch", [_P, _P])
 _sig("aiwc_rf_forest_export_host", [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_free", [_P], None)
 _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
@@ -71,16 +72,28 @@ _sig("aiwc_rf_server_create", [_P, _i32, _i64, _i32, _i32, _P])
 _sig("aiwc_rf_server_submit", [_P, _P, _i64, _P, _P])
 _sig("aiwc_rf_server_poll", [_P, _P, _P, _i32, _P])
 _sig("aiwc_rf_server_drain", [_P])
-_sig("aiwc_rf_server_stats", [_P, _P, _P, _P])
+_sig("aiwc_rf_server_stats", [_P, _P, _P, _P, _P])
 _sig("aiwc_rf_server_free", [_P], None)
 _sig("aiwc_rf_last_error", [], ctypes.c_char_p)
 
 SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
-           "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_tree_sizes",
+           "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_launch",
+           "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
            "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
            "aiwc_rf_heldout_rows", "aiwc_rf_tune_sa", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
+
+
+class LaunchInfo(ctypes.Structure):
+    """aiwc_rf_launch_info: the grow kernel's launch shape a fit used."""
+
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("wide_limit", ctypes.c_int32),
+                ("big_cols", ctypes.c_int32), ("grid", ctypes.c_int32), ("wide_phase", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("graph_reused", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class RFError(RuntimeError):
@@ -117,6 +130,19 @@ def _dev(t, dtype, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _release(obj, free_name: str):
+    """Free a handle from __del__; at interpreter shutdown the library and this
+    module's globals may already be gone, and then there is nothing to do."""
+    h = getattr(obj, "handle", None)
+    if not h:
+        return
+    obj.handle = None
+    try:
+        getattr(_L, free_name)(h)
+    except Exception:  # shutdown: module globals torn down
+        pass
+
+
 def _host(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -145,9 +171,7 @@ class Binner:
         return self.export()[0]
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _L.aiwc_rf_binner_free(self.handle)
-            self.handle = None
+        _release(self, "aiwc_rf_binner_free")
 
 
 def aiwc_rf_bin(X, device_id, n_devices: int, max_bins: int = 256, binner: Binner | None = None, codes=None,
@@ -197,11 +221,18 @@ class Forest:
         return tot.value
 
     def stats(self, forest_index: int = 0):
-        """(work, grow_ms): work = [searched rows, searched nodes, partitioned rows, max levels]."""
-        w = np.zeros(4, np.int64)
+        """(work, grow_ms): work = [searched rows, searched nodes, partitioned rows, max levels,
+        LDS histogram bin adds]."""
+        w = np.zeros(5, np.int64)
         ms = ctypes.c_float()
         _check(_L.aiwc_rf_forest_stats(self.handle, forest_index, _host(w), ctypes.byref(ms)), "aiwc_rf_forest_stats")
         return w, ms.value
+
+    def launch(self) -> dict:
+        """The grow kernel's launch shape this fit used (aiwc_rf_forest_launch)."""
+        info = LaunchInfo()
+        _check(_L.aiwc_rf_forest_launch(self.handle, ctypes.byref(info)), "aiwc_rf_forest_launch")
+        return info.as_dict()
 
     def tree_sizes(self, forest_index: int = 0, tree_begin: int = 0, tree_end: int | None = None) -> np.ndarray:
         if tree_end is None:
@@ -233,9 +264,7 @@ class Forest:
         return out
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _L.aiwc_rf_forest_free(self.handle)
-            self.handle = None
+        _release(self, "aiwc_rf_forest_free")
 
 
 def make_params(num_trees: int, mtry: int, min_node_size: int, bootstrap: bool = True, seed: int = 1) -> Params:
@@ -448,6 +477,7 @@ class ServerStats:
     rows: int
     batches: int
     peak_bytes: int
+    memory_waits: int
 
 
 class Server:
@@ -486,10 +516,10 @@ class Server:
         _check(_L.aiwc_rf_server_drain(self.handle), "aiwc_rf_server_drain")
 
     def stats(self) -> ServerStats:
-        r, b, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _check(_L.aiwc_rf_server_stats(self.handle, ctypes.byref(r), ctypes.byref(b), ctypes.byref(p)),
-               "aiwc_rf_server_stats")
-        return ServerStats(r.value, b.value, p.value)
+        r, b, p, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_L.aiwc_rf_server_stats(self.handle, ctypes.byref(r), ctypes.byref(b), ctypes.byref(p),
+                                       ctypes.byref(w)), "aiwc_rf_server_stats")
+        return ServerStats(r.value, b.value, p.value, w.value)
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -497,4 +527,7 @@ class Server:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals torn down
+            pass

@@ -53,13 +53,24 @@ def test_argument_checks_without_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.aiwc_rf_bin(buf, buf, 0, 3, 1, 8, ctypes.byref(h), buf, None) == -1
     assert lib.aiwc_rf_bin(buf, buf, 10, 256, 1, 8, ctypes.byref(h), buf, None) == -1
+    # column ids stay below the leaf marker 255: at most 254 features
+    assert lib.aiwc_rf_bin(buf, buf, 10, 255, 1, 8, ctypes.byref(h), buf, None) == -1
+    assert b"254" in lib.aiwc_rf_last_error()
+    rc = lib.aiwc_rf_bin(buf, buf, 10, 254, 1, 8, ctypes.byref(h), buf, None)
+    assert rc != 0 and b"p must" not in lib.aiwc_rf_last_error()  # passes the check, then needs a GPU
     assert lib.aiwc_rf_bin(buf, buf, 10, 3, 0, 8, ctypes.byref(h), buf, None) == -1
     assert lib.aiwc_rf_bin(buf, buf, 10, 3, 1, 1, ctypes.byref(h), buf, None) == -1
     lib.aiwc_rf_binner_from_counts.argtypes = [P, ctypes.c_int32, P]
     counts = (ctypes.c_int32 * 3)(4, 0, 2)
     assert lib.aiwc_rf_binner_from_counts(counts, 3, ctypes.byref(h)) == -1
+    many = (ctypes.c_int32 * 256)(*([2] * 256))
+    assert lib.aiwc_rf_binner_from_counts(many, 256, ctypes.byref(h)) == -1
+    assert b"n_cols" in lib.aiwc_rf_last_error()
+    rc = lib.aiwc_rf_binner_from_counts(many, 255, ctypes.byref(h))
+    assert rc != 0 and b"n_cols" not in lib.aiwc_rf_last_error()  # 255 columns pass the check
     lib.aiwc_rf_server_submit.argtypes = [P, P, ctypes.c_int64, P, P]
     assert lib.aiwc_rf_server_submit(None, None, 1, None, None) == -1
+    assert b"null" in lib.aiwc_rf_last_error()  # submit failures set the message too
 
 
 def test_group_and_heldout_argument_checks_without_gpu(lib):

@@ -103,3 +103,15 @@ def test_fixed_point_rounds_half_even(oracle):
     y = np.array([0.5 / 65536, 1.5 / 65536, -0.5 / 65536, -2.5 / 65536, 64.0, -64.0, 1.0 / 3.0])
     got = oracle.y_fixed(y)
     assert got.tolist() == [0, 2, 0, -2, 64 << 16, -(64 << 16), 21845]
+
+
+def test_column_limit_below_leaf_marker(oracle):
+    """Column ids must stay below the leaf marker 255: 254 features (255 code
+    columns with the device) are accepted, 255 features are rejected."""
+    rng = np.random.default_rng(3)
+    dev = np.zeros(6, np.int32)
+    b = oracle.bin(rng.normal(size=(6, 254)).astype(np.float32), dev, 1, 4)
+    assert b.codes.shape == (6, 255)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bin(rng.normal(size=(6, 255)).astype(np.float32), dev, 1, 4)
+    assert e.value.rc == oracle.EINVAL

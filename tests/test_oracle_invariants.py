@@ -160,3 +160,23 @@ def test_statistical_sanity_held_out(oracle):
     _, yhat = oracle.predict(f, b.codes[test])
     mae = np.abs(yhat - ds.y[test]).mean()
     assert mae < 0.5 * np.abs(ds.y - ds.y.mean()).mean()
+
+
+def test_last_code_column_splits_and_is_not_a_leaf(oracle):
+    """With 255 code columns the last one (id 254) is an ordinary split column,
+    distinct from the leaf marker; 256 columns are rejected."""
+    n, C = 8, 255
+    codes = np.zeros((n, C), np.uint8)
+    codes[:, C - 1] = np.arange(n) % 2
+    n_bins = np.full(C, 2, np.int32)
+    y = np.where(codes[:, C - 1] == 1, 1.0, -1.0)
+    f = oracle.fit(codes, n_bins, y, 1, C, 1, bootstrap=False)
+    t = f.tree(0)
+    assert t["col"][0] == C - 1 and t["col"][0] != oracle.LEAF
+    assert list(t["col"][1:]) == [oracle.LEAF, oracle.LEAF]
+    _, yhat = oracle.predict(f, codes)
+    assert np.array_equal(yhat, y)
+    wide = np.zeros((n, 256), np.uint8)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.fit(wide, np.full(256, 2, np.int32), y, 1, 1, 1)
+    assert e.value.rc == oracle.EINVAL
