@@ -31,7 +31,12 @@ def test_alone_equals_mixed(served):
     reqs = [np.ascontiguousarray(codes[rng.integers(0, codes.shape[0], size=s)]) for s in sizes]
     alone = [rf.aiwc_rf_predict(forest, to_dev(r)).cpu().numpy() for r in reqs]
     log("serve mixed stream")
-    srv = rf.Server(forest, memory_budget_bytes=200_000, max_batch_rows=4096, n_streams=3)
+    # a row slot costs 2 * 15 + 24 = 54 bytes of the budget (device codes, sum and
+    # answer; pinned codes and answer), so 280000 bytes hold about 5100 rows: the
+    # 4096-row request fits, the whole stream (10495 rows) does not, and later
+    # requests wait for retiring batches
+    budget = 280_000
+    srv = rf.Server(forest, memory_budget_bytes=budget, max_batch_rows=4096, n_streams=3)
     outs = [np.zeros(r.shape[0]) for r in reqs]
     tickets = [srv.submit(r, o) for r, o in zip(reqs, outs)]
     srv.drain()
@@ -42,8 +47,9 @@ def test_alone_equals_mixed(served):
         assert np.array_equal(a.view(np.uint64), o.view(np.uint64))
     st = srv.stats()
     assert st.rows == sum(sizes)
-    assert st.peak_bytes <= 200_000
+    assert st.peak_bytes <= budget
     assert st.batches < len(sizes)  # requests were batched together
+    assert st.memory_waits > 0  # and some waited for memory
     srv.close()
 
 
@@ -54,4 +60,12 @@ def test_admission_limits(served):
     with pytest.raises(rf.RFError) as e:
         srv.submit(big, np.zeros(200))
     assert e.value.rc == rf.ENOMEM
+    assert "max_batch_rows" in str(e.value)
+    srv.close()
+    # a request larger than the whole budget can never be admitted
+    srv = rf.Server(forest, memory_budget_bytes=10_000, max_batch_rows=1000, n_streams=1)
+    with pytest.raises(rf.RFError) as e:
+        srv.submit(big, np.zeros(200))
+    assert e.value.rc == rf.ENOMEM
+    assert "memory budget" in str(e.value)
     srv.close()
