@@ -1,19 +1,26 @@
 """Benchmark of the random-forest performance model on one MI355X.
 
-python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+python bench.py [--steps K] [--warmup W] [--workload c4|c1|c2|c3|c5|studies|tune|lds|copy]
 
-One step is one pass of the whole hot path over one batch of synthetic input
-that is already resident in device memory: quantile binning of the feature
-matrix, the forest fit (fixed-point response, bootstrap, per-node mtry draw,
-histogram and split search, partition, leaves) and the prediction of every row.
+The default workload is the tuning grid (c4), on which the headline metric is
+quoted: one step fits all 1700 forests in one fused graph launch (the timed
+value) and then again as one launch sequence per forest (the plain comparison).
+For the single-forest workloads one step is one pass of the whole hot path over
+one batch of synthetic input that is already resident in device memory:
+quantile binning of the feature matrix, the forest fit (fixed-point response,
+bootstrap, per-node mtry draw, histogram and split search, partition, leaves)
+and the prediction of every row.  Launch shapes are the library's defaults
+(reproducible, and the ones the committed profiles were taken with); --tune
+lets the autotuner pick them in the warmup instead.
 
 Workloads (synthetic, shaped like the paper's frame: 37 kernels x 4 sizes x 15
 devices, 34 features; see paper_1811_00156_amd/synth.py):
   c1  2220 rows, 64 bins, 100 trees, mtry 6, min.node.size 5
-  c2  2220 rows, 256 bins, 2000 trees, mtry 12, min.node.size 1   (default)
+  c2  2220 rows, 256 bins, 2000 trees, mtry 12, min.node.size 1
   c3  200000 rows x 64 features + 32 devices, 256 bins, 500 trees, mtry 16, min.node.size 5
   c4  2220 rows, 64 bins, 10 folds x mtry 1..34 x min.node.size {1,3,5,7,9} = 1700 forests x 256 trees,
-      fused single launch vs one launch sequence per forest
+      fused single launch vs one launch sequence per forest   (default; the line also carries the
+      200000-row forest's grow-kernel roofline and the serving p50/p99 at 2000 QPS)
   c5  serving: the c3 forest answers Poisson request streams of 1..4096 rows
   studies  the kernel studies of Sec. III-C on 2220 rows, 256 bins, num.trees 505, mtry 30,
       min.node.size 9: leave-one-kernel-out (37 forests) and training on i = 1..36 random
@@ -21,10 +28,17 @@ devices, 34 features; see paper_1811_00156_amd/synth.py):
   tune  the annealing search of Sec. III-B on 2220 rows, 256 bins: num.trees 10..1000, mtry 1..35,
       min.node.size 1..50 from (500, 17, 5), 10 levels x 32 proposals fitted together per level
 
+  lds  LDS atomic add throughput (the probe library): the second ceiling of the grow kernel
+  copy  a plain device copy (calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE)
+
 Prints ONE JSON line.  `value` is whole-step throughput in rows x trees per
 second (c5: rows per second).  `roofline` describes the tree-growing kernel:
-algorithmic bytes per launch over its event-timed duration.  `cpu_baseline` is
-the CPU oracle timed on the host cores on a bounded sample of the same work.
+algorithmic bytes per launch (the per-row model of the tree-growing steps:
+mtry candidate codes + 8 bytes of response + 1 of weight + 4 of row index per
+searched row and level, 10 bytes per partitioned row and level) over its
+event-timed duration; `lds_roofline` sets its LDS histogram adds against the
+probe's measured rate.  `cpu_baseline` is the CPU oracle timed on the host
+cores, at all of them and at one, on a bounded sample of the same work.
 """
 from __future__ import annotations
 
@@ -55,36 +69,41 @@ WORKLOADS = {
 METRIC = "forest fit rows·trees/s (fused grid vs plain); predict rows/s + p99 latency"
 
 
-FIXED_SHAPE = False
+TUNE = False
 
 
 def tune_flag():
-    """FIT_TUNE unless --fixed-shape asks for the launch shape of the environment."""
+    """FIT_TUNE when --tune asks the autotuner to pick the launch shape, else the
+    library's default shape (or the one the environment names)."""
     from paper_1811_00156_amd import rf
 
-    return 0 if FIXED_SHAPE else rf.FIT_TUNE
+    return rf.FIT_TUNE if TUNE else 0
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def grow_bytes(work, mtry, total_nodes):
-    """Algorithmic bytes of the tree-growing kernel.
+def grow_bytes(work, mtry):
+    """Algorithmic bytes of the tree-growing kernel, per the method's own row
+    counts: every in-bag row of a node whose split is searched costs its code in
+    each of the mtry candidate columns, its 8-byte fixed-point response, its
+    1-byte bootstrap weight and its 4-byte row index (mtry + 13 bytes); every row
+    of a node that splits costs 10 bytes to route into a child (its code in the
+    split column, index and weight read, index written)."""
+    searched_rows, part_rows = int(work[0]), int(work[2])
+    return searched_rows * (mtry + 13) + part_rows * 10
 
-    Every node whose split is searched reads, for each of its in-bag rows, the
-    8-byte row entry (row, weight, fixed-point response) and the row's code in
-    each of its mtry candidate columns; every node that splits reads each entry
-    and its code in the split column and writes the entry to a child (8 + 1 + 8);
-    every node writes its 8-byte node word and 4-byte weight."""
-    searched_rows, _, part_rows, _ = (int(x) for x in work)
-    return searched_rows * (8 + mtry) + part_rows * 17 + total_nodes * 12
+
+TRAFFIC_SOURCES = ["paper_1811_00156_amd/csrc/fit.hip", "paper_1811_00156_amd/csrc/device.h",
+                   "paper_1811_00156_amd/csrc/api.cpp", "paper_1811_00156_amd/csrc/internal.h"]
 
 
 def measured_traffic(kernel_key):
     """HBM bytes per launch from the rocprofv3 counter runs summarised in
     profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    the kernel source has changed since the counters were taken."""
+    the kernel, or the host code that picks its launch shape, has changed since
+    the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -101,56 +120,117 @@ def measured_traffic(kernel_key):
     return rec["traffic_bytes"]
 
 
-CPU_TARGET_S = 12.0  # seconds of oracle work per CPU baseline
+def lds_peak():
+    """The probe's LDS atomic add rates (lane-adds/s): ds_add_u64 with the lanes
+    of an instruction on distinct consecutive bins (the conflict-free peak) and
+    on pseudo-random bins (the histogram build's pattern)."""
+    import ctypes
 
-
-def run_cpu_baseline(wl, ds, probe_trees):
-    """The oracle's whole-step throughput on the host: bin once, then fit and
-    predict trees of the same forest (repeating the whole forest when it takes
-    less) until about CPU_TARGET_S seconds of work; a first pass of probe_trees
-    trees sizes the sample."""
-    from oracle import oracle as O
-
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    b = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
-    t_bin = time.perf_counter() - t0
-    nt = wl["num_trees"]
-
-    def fit_predict(k):
-        f = O.fit(b.codes, b.n_bins, ds.y, nt, wl["mtry"], wl["min_node"], seed=1, trees=range(k), n_threads=cores)
-        O.predict(f, b.codes)
-
-    probe = min(probe_trees, nt)
-    t0 = time.perf_counter()
-    fit_predict(probe)
-    per_tree = (time.perf_counter() - t0) / probe
-    want = max(probe, int(CPU_TARGET_S / max(per_tree, 1e-9)))
-    # in pieces of about an eighth of the estimate, stopping once the target
-    # time is spent (the probe can misjudge the host's sustained rate)
-    piece = max(probe, want // 8)
-    t0 = time.perf_counter()
-    done = 0
-    el = 0.0
-    while done < want and (done == 0 or el < CPU_TARGET_S):
-        k = min(nt, want - done, piece)
-        fit_predict(k)
-        done += k
-        el = time.perf_counter() - t0
-    # one step = bin + fit and predict the whole forest; fit and predict are linear in trees
-    step_s = t_bin + el * nt / done
-    return {"value": ds.n * nt / step_s, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
-            "sample": f"bin all {ds.n} rows ({t_bin:.2f} s) + fit and predict {done} trees of the {nt}-tree forest "
-                      f"({el:.1f} s), scaled to one step"}
-
-
-def bench_forest(args, wl_name):
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1811_00156_amd", "libaiwc_rf_probe.so"))
+    lib.aiwc_rf_probe_lds_add.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_void_p] * 3
+    lib.aiwc_rf_probe_last_error.restype = ctypes.c_char_p
     import torch
 
-    from paper_1811_00156_amd import rf, synth
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for width in (64, 32):
+        for pattern, name in ((0, "distinct"), (1, "random")):
+            r, ms = ctypes.c_double(), ctypes.c_double()
+            rc = lib.aiwc_rf_probe_lds_add(width, pattern, 8 * cus, 2000, ctypes.byref(r), ctypes.byref(ms), None)
+            if rc != 0:
+                raise RuntimeError(f"LDS probe failed ({rc}): {lib.aiwc_rf_probe_last_error().decode()}")
+            out[f"u{width}_{name}"] = r.value
+    return out
 
-    wl = WORKLOADS[wl_name]
-    ds = synth.d1() if wl["data"] == "d1" else synth.d3()
+
+def lds_roofline(work_hist, ms, peaks):
+    """The grow kernel's LDS histogram adds per second against the probe."""
+    achieved = float(work_hist) / (ms / 1000.0)
+    return {"kernel": "k_grow", "bound": "lds_atomic", "achieved": achieved, "unit": "adds/s",
+            "peak": peaks["u64_distinct"], "frac": achieved / peaks["u64_distinct"],
+            "peak_random_bins": peaks["u64_random"], "frac_random_bins": achieved / peaks["u64_random"],
+            "adds_per_launch": int(work_hist),
+            "peak_source": "ds_add_u64 probe (libaiwc_rf_probe.so), 8 workgroups of 256 threads per CU"}
+
+
+# ---------------------------------------------------------------------------- CPU baseline
+CPU_TARGET_S = 10.0  # seconds of oracle work per thread count
+
+
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_legs(leg, unit):
+    """leg(n_threads) -> (rate, sample description), timed at every host thread
+    and at one; the all-threads rate is the baseline's value."""
+    cores = host_threads()
+    v, smp = leg(cores)
+    v1, smp1 = leg(1)
+    return {"value": v, "unit": unit, "cores": cores, "kind": "oracle", "sample": smp,
+            "value_1thread": v1, "sample_1thread": smp1, "cpu_model": cpu_model()}
+
+
+def forest_cpu_leg(wl, ds, probe_trees):
+    """The oracle's whole-step throughput: bin once, then fit and predict trees of
+    the same forest (repeating the whole forest when it takes less) until about
+    CPU_TARGET_S seconds of work; a first pass of probe_trees trees sizes the
+    sample."""
+    from oracle import oracle as O
+
+    def leg(threads):
+        t0 = time.perf_counter()
+        b = O.bin(ds.X, ds.device, ds.n_devices, wl["bins"])
+        t_bin = time.perf_counter() - t0
+        nt = wl["num_trees"]
+
+        def fit_predict(k):
+            f = O.fit(b.codes, b.n_bins, ds.y, nt, wl["mtry"], wl["min_node"], seed=1, trees=range(k),
+                      n_threads=threads)
+            O.predict(f, b.codes)
+
+        probe = min(max(1, probe_trees * threads // host_threads()), nt)
+        t0 = time.perf_counter()
+        fit_predict(probe)
+        per_tree = (time.perf_counter() - t0) / probe
+        want = max(probe, int(CPU_TARGET_S / max(per_tree, 1e-9)))
+        # in pieces of about an eighth of the estimate, stopping once the target
+        # time is spent (the probe can misjudge the host's sustained rate)
+        piece = max(probe, want // 8)
+        t0 = time.perf_counter()
+        done = 0
+        el = 0.0
+        while done < want and (done == 0 or el < CPU_TARGET_S):
+            k = min(nt, want - done, piece)
+            fit_predict(k)
+            done += k
+            el = time.perf_counter() - t0
+        # one step = bin + fit and predict the whole forest; fit and predict are linear in trees
+        step_s = t_bin + el * nt / done
+        return ds.n * nt / step_s, (f"{threads} thread(s): bin all {ds.n} rows ({t_bin:.2f} s) + fit and predict "
+                                    f"{done} trees of the {nt}-tree forest ({el:.1f} s), scaled to one step")
+
+    return leg
+
+
+# ---------------------------------------------------------------------------- single forests
+def fit_forest_steps(wl, ds, steps, warmup, tag, predict_all=True):
+    """Timed bin + fit (+ predict) steps of one forest workload.  Returns the
+    step wall time and medians of each part, the last forest and its work."""
+    import torch
+
+    from paper_1811_00156_amd import rf
+
     dev = torch.device("cuda:0")
     X = torch.from_numpy(ds.X).to(dev)
     did = torch.from_numpy(ds.device).to(dev)
@@ -161,11 +241,12 @@ def bench_forest(args, wl_name):
     def step():
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
         forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=tune_flag())
-        rf.aiwc_rf_predict(forest, codes, out=out)
+        if predict_all:
+            rf.aiwc_rf_predict(forest, codes, out=out)
         return forest, binner
 
-    for i in range(args.warmup):
-        log(f"{wl_name} warmup {i}")
+    for i in range(warmup):
+        log(f"{tag} warmup {i}")
         keep = step()
     torch.cuda.synchronize()
     keep = None
@@ -174,13 +255,14 @@ def bench_forest(args, wl_name):
     forests = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ev[0].record()
         codes, binner = rf.aiwc_rf_bin(X, did, ds.n_devices, wl["bins"])
         ev[1].record()
         forest = rf.aiwc_rf_fit(codes, binner, y, prm, flags=tune_flag())
         ev[2].record()
-        rf.aiwc_rf_predict(forest, codes, out=out)
+        if predict_all:
+            rf.aiwc_rf_predict(forest, codes, out=out)
         ev[3].record()
         ev[3].synchronize()
         bin_ms.append(ev[0].elapsed_time(ev[1]))
@@ -189,46 +271,62 @@ def bench_forest(args, wl_name):
         grow_ms.append(forest.stats()[1])
         if forests:
             forests.pop()  # release the previous step's forest
-        forests.append((forest, binner))
-        log(f"{wl_name} step {i}: bin {bin_ms[-1]:.2f} ms fit {fit_ms[-1]:.2f} ms (grow {grow_ms[-1]:.2f}) "
+        forests.append((forest, binner, codes))
+        log(f"{tag} step {i}: bin {bin_ms[-1]:.2f} ms fit {fit_ms[-1]:.2f} ms (grow {grow_ms[-1]:.2f}) "
             f"predict {pred_ms[-1]:.3f} ms")
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1000.0 / args.steps
-    forest = forests[-1][0]
+    ms_step = (time.perf_counter() - t0) * 1000.0 / steps
+    forest, binner, codes = forests[-1]
     work, _ = forest.stats()
-    total_nodes = forest.total_nodes()
-    gbytes = grow_bytes(work, wl["mtry"], total_nodes)
-    g_ms = float(np.mean(grow_ms))
+    return dict(ms_step=ms_step, bin=float(np.median(bin_ms)), fit=float(np.median(fit_ms)),
+                grow=float(np.mean(grow_ms)), predict=float(np.median(pred_ms)), forest=forest, binner=binner,
+                codes=codes, work=work, launch=forest.launch())
+
+
+def grow_roofline(work, mtry, g_ms, key, peaks=None):
+    gbytes = grow_bytes(work, mtry)
     achieved = gbytes / (g_ms / 1000.0) / 1e9
+    r = {"kernel": "k_grow", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key),
+         "algorithmic_bytes_per_launch": int(gbytes), "avg_launch_ms": g_ms}
+    return r
+
+
+def bench_forest(args, wl_name):
+    from paper_1811_00156_amd import synth
+
+    wl = WORKLOADS[wl_name]
+    ds = synth.d1() if wl["data"] == "d1" else synth.d3()
+    r = fit_forest_steps(wl, ds, args.steps, args.warmup, wl_name)
+    work = r["work"]
     rows_trees = ds.n * wl["num_trees"]
     res = {
-        "metric": METRIC, "value": rows_trees / (ms_step / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "metric": METRIC, "value": rows_trees / (r["ms_step"] / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
         "config": {"workload": f"{wl_name}: {ds.n} rows x {ds.p} features + device ({ds.n_devices} levels), "
                                f"{wl['bins']} bins, num.trees {wl['num_trees']}, mtry {wl['mtry']}, "
                                f"min.node.size {wl['min_node']}; bin + fit + predict all rows",
                    "rows": ds.n, "num_trees": wl["num_trees"], "bins": wl["bins"], "mtry": wl["mtry"],
-                   "min_node_size": wl["min_node"]},
-        "breakdown_ms": {"bin": float(np.median(bin_ms)), "fit": float(np.median(fit_ms)),
-                         "grow_kernel": float(np.median(grow_ms)), "predict": float(np.median(pred_ms))},
-        "fit_rows_trees_per_s": rows_trees / (float(np.median(fit_ms)) / 1000.0),
-        "predict_rows_per_s": ds.n / (float(np.median(pred_ms)) / 1000.0),
-        "tree_stats": {"total_nodes": int(total_nodes), "searched_rows": int(work[0]), "searched_nodes": int(work[1]),
-                       "partitioned_rows": int(work[2]), "max_levels": int(work[3])},
-        "roofline": {"kernel": "k_grow", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"k_grow@{wl_name}"),
-                     "algorithmic_bytes_per_launch": int(gbytes), "avg_launch_ms": g_ms},
+                   "min_node_size": wl["min_node"], "launch": r["launch"]},
+        "breakdown_ms": {"bin": r["bin"], "fit": r["fit"], "grow_kernel": r["grow"], "predict": r["predict"]},
+        "fit_rows_trees_per_s": rows_trees / (r["fit"] / 1000.0),
+        "predict_rows_per_s": ds.n / (r["predict"] / 1000.0),
+        "tree_stats": {"total_nodes": int(r["forest"].total_nodes()), "searched_rows": int(work[0]),
+                       "searched_nodes": int(work[1]), "partitioned_rows": int(work[2]), "max_levels": int(work[3]),
+                       "lds_bin_adds": int(work[4])},
+        "roofline": grow_roofline(work, wl["mtry"], r["grow"], f"k_grow@{wl_name}"),
     }
+    if not args.no_lds:
+        res["lds_roofline"] = lds_roofline(work[4], r["grow"], lds_peak())
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sample = {"c1": 100, "c2": 200, "c3": 16}.get(wl_name, 16)
-        res["cpu_baseline"] = run_cpu_baseline(wl, ds, sample)
-    forests.clear()
+        res["cpu_baseline"] = cpu_legs(forest_cpu_leg(wl, ds, sample), "rows·trees/s")
     return res
 
 
+# ---------------------------------------------------------------------------- the tuning grid
 def bench_grid(args):
     import torch
 
@@ -255,8 +353,7 @@ def bench_grid(args):
         torch.cuda.synchronize()
         return g, (time.perf_counter() - t0) * 1000.0
 
-    # the warmup runs both paths, so that each one's launch shapes are tuned
-    # before the timed steps
+    # the warmup runs both paths (and tunes each one's launch shape under --tune)
     for i in range(args.warmup):
         log(f"grid warmup {i}")
         g, _ = run(rf.FIT_FUSED | tune_flag())
@@ -268,78 +365,122 @@ def bench_grid(args):
         g, ms = run(rf.FIT_FUSED | tune_flag())
         fused_ms.append(ms)
         grow_ms.append(g.stats(0)[1])
-        log(f"grid fused step {i}: {ms:.1f} ms (grow {grow_ms[-1]:.1f} ms)")
-        del g
-        g, ms = run(rf.FIT_PLAIN | tune_flag())
+        log(f"grid fused step {i}: {ms:.1f} ms (graph {grow_ms[-1]:.1f} ms)")
+        if i + 1 < args.steps:
+            del g
+        else:
+            fused = g
+        gp, ms = run(rf.FIT_PLAIN | tune_flag())
         plain_ms.append(ms)
         log(f"grid plain step {i}: {ms:.1f} ms")
-        del g
+        del gp
     f_ms, p_ms = float(np.median(fused_ms)), float(np.median(plain_ms))
+    # the kernel's work: per forest (its own mtry in the byte model)
+    gbytes = 0
+    work = np.zeros(5, np.int64)
+    for k, (_, m, _) in enumerate(combos):
+        w, _ = fused.stats(k)
+        gbytes += grow_bytes(w, m)
+        work += w
+    g_ms = float(np.mean(grow_ms))
+    achieved = gbytes / (g_ms / 1000.0) / 1e9
+    launch = fused.launch()
     # out-of-bag scoring of every forest of the grid (the tuning objective), after the fit
-    g, _ = run(rf.FIT_FUSED | tune_flag())
     oob_ms = []
     for i in range(max(args.steps, 1)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        o = rf.aiwc_rf_oob_error(g, codes, y)
+        o = rf.aiwc_rf_oob_error(fused, codes, y)
         oob_ms.append((time.perf_counter() - t0) * 1000.0)
     best = int(np.argmin(o.mse))
     log(f"grid oob: {float(np.median(oob_ms)):.1f} ms; lowest OOB MSE {o.mse[best]:.4f} at forest {best} "
         f"(fold {combos[best][0]}, mtry {combos[best][1]}, min.node.size {combos[best][2]})")
-    del g
+    del fused
     res = {
         "metric": METRIC, "value": rows_trees / (f_ms / 1000.0), "unit": "rows·trees/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
-        "config": {"workload": "c4: 2220 rows, 64 bins, 10 CV folds x mtry 1..34 x min.node.size {1,3,5,7,9} "
-                               "= 1700 forests x 256 trees, one fused launch", "forests": len(params)},
-        "plain_ms": p_ms, "plain_rows_trees_per_s": rows_trees / (p_ms / 1000.0), "fused_speedup": p_ms / f_ms,
-        "grow_kernel_ms": float(np.median(grow_ms)),
+        "config": {"workload": "c4: 2220 rows x 34 features + device (15 levels), 64 bins, 10 CV folds x "
+                               "mtry 1..34 x min.node.size {1,3,5,7,9} = 1700 forests x 256 trees, "
+                               "one fused graph launch per step (value); the same forests as 1700 plain "
+                               "launch sequences (plain_ms)",
+                   "forests": len(params), "trees": 256 * len(params), "rows_trees": rows_trees, "launch": launch},
+        "fused_ms": f_ms, "plain_ms": p_ms, "plain_rows_trees_per_s": rows_trees / (p_ms / 1000.0),
+        "fused_speedup": p_ms / f_ms, "fused_ms_runs": fused_ms, "plain_ms_runs": plain_ms,
+        "roofline": {"kernel": "k_grow", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_grow@c4"),
+                     "algorithmic_bytes_per_launch": int(gbytes), "avg_launch_ms": g_ms},
+        "tree_stats": {"searched_rows": int(work[0]), "searched_nodes": int(work[1]), "partitioned_rows": int(work[2]),
+                       "lds_bin_adds": int(work[4])},
         "oob_ms": float(np.median(oob_ms)), "oob_rows_trees_per_s": rows_trees / (float(np.median(oob_ms)) / 1000.0),
     }
+    if not args.no_lds:
+        res["lds_roofline"] = lds_roofline(work[4], g_ms, lds_peak())
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         ob = O.bin(ds.X, ds.device, ds.n_devices, 64)
-        # random forests of the grid, whole, until about CPU_TARGET_S seconds of work
-        rng = np.random.default_rng(0)
-        pick = rng.permutation(len(combos))
-        t0 = time.perf_counter()
-        rt = used = 0
-        for k in pick:
-            f, m, mn = combos[k]
-            train = np.nonzero(folds != f)[0]
-            O.fit(ob.codes, ob.n_bins, ds.y, 256, m, mn, seed=1, train_rows=train, n_threads=cores)
-            rt += train.shape[0] * 256
-            used += 1
-            if time.perf_counter() - t0 >= CPU_TARGET_S:
-                break
-        el = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{used} random forests of the grid (256 trees each), {el:.1f} s"}
+
+        def leg(threads):
+            # random forests of the grid, whole, until about CPU_TARGET_S seconds of work
+            pick = np.random.default_rng(0).permutation(len(combos))
+            t0 = time.perf_counter()
+            rt = used = 0
+            for k in pick:
+                f, m, mn = combos[k]
+                train = np.nonzero(folds != f)[0]
+                O.fit(ob.codes, ob.n_bins, ds.y, 256, m, mn, seed=1, train_rows=train, n_threads=threads)
+                rt += train.shape[0] * 256
+                used += 1
+                if time.perf_counter() - t0 >= CPU_TARGET_S:
+                    break
+            el = time.perf_counter() - t0
+            return rt / el, f"{threads} thread(s): {used} random forests of the grid (256 trees each), {el:.1f} s"
+
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_legs(leg, "rows·trees/s")
+    if not args.no_extras:
+        res.update(extra_legs(args))
     return res
 
 
-def bench_serve(args):
-    import torch
+def extra_legs(args):
+    """The 200000-row forest's grow-kernel roofline and the serving latency of
+    that forest at 2000 QPS, beside the grid's line."""
+    from paper_1811_00156_amd import synth
 
-    from paper_1811_00156_amd import rf, synth
-
-    wl = WORKLOADS["c5"]
+    wl = WORKLOADS["c3"]
     ds = synth.d3()
-    dev = torch.device("cuda:0")
-    codes, binner = rf.aiwc_rf_bin(torch.from_numpy(ds.X).to(dev), torch.from_numpy(ds.device).to(dev),
-                                   ds.n_devices, wl["bins"])
-    forest = rf.aiwc_rf_fit(codes, binner, torch.from_numpy(ds.y).to(dev),
-                            rf.make_params(wl["num_trees"], wl["mtry"], wl["min_node"], True, 1))
-    host_codes = codes.cpu().numpy()
-    n_req = args.requests
+    r = fit_forest_steps(wl, ds, 3, 1, "c3", predict_all=False)
+    rows_trees = ds.n * wl["num_trees"]
+    c3 = {"workload": "c3: 200000 rows x 64 features + device (32 levels), 256 bins, num.trees 500, mtry 16, "
+                      "min.node.size 5; bin + fit", "launch": r["launch"],
+          "ms_per_step": r["ms_step"], "fit_ms": r["fit"], "fit_rows_trees_per_s": rows_trees / (r["fit"] / 1000.0),
+          "roofline": grow_roofline(r["work"], wl["mtry"], r["grow"], "k_grow@c3"),
+          "lds_bin_adds": int(r["work"][4])}
+    if not args.no_lds:
+        c3["lds_roofline"] = lds_roofline(r["work"][4], r["grow"], lds_peak())
+    log(f"c3: fit {r['fit']:.1f} ms, grow {r['grow']:.1f} ms, frac {c3['roofline']['frac']:.3f}")
+    sv = serve_points(r["forest"], r["codes"].cpu().numpy(), ds.n, args.requests, load_fracs=(),
+                      fixed_qps=(2000.0,))
+    c5 = {"workload": "c5: serving the c3 forest; Poisson arrivals at 2000 QPS, 1..4096 rows per request "
+                      "(log-uniform); arrival to answer in host memory",
+          "saturated_rows_per_s": sv["saturated"]["rows_per_s"], "at_2000qps": sv["points"]["2000qps"]}
+    log(f"c5: saturated {c5['saturated_rows_per_s']:.3g} rows/s; 2000 QPS p50 {c5['at_2000qps']['p50_ms']:.3f} ms "
+        f"p99 {c5['at_2000qps']['p99_ms']:.3f} ms")
+    return {"c3": c3, "c5": c5}
+
+
+# ---------------------------------------------------------------------------- serving
+def serve_points(forest, host_codes, n_rows, n_req, load_fracs=(0.25, 0.5, 0.8), fixed_qps=(2000.0,)):
+    """Saturated rows/s (median of three closed-loop passes after a warmup pass)
+    and open-loop p50/p99 latency at fractions of it and at fixed rates."""
+    from paper_1811_00156_amd import rf, synth
 
     def stream(qps, seed_shift=0):
         arrivals, sizes, row_seed = synth.request_stream(n_req, qps)
         rng = np.random.default_rng(row_seed + seed_shift)
-        reqs = [np.ascontiguousarray(host_codes[rng.integers(0, ds.n, size=int(s))]) for s in sizes]
+        reqs = [np.ascontiguousarray(host_codes[rng.integers(0, n_rows, size=int(s))]) for s in sizes]
         return arrivals, reqs
 
     def serve(arrivals, reqs, open_loop=True):
@@ -358,7 +499,8 @@ def bench_serve(args):
         srv.close()
         rows = sum(r.shape[0] for r in reqs)
         return {"rows_per_s": rows / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3), "batches": st.batches, "requests": len(reqs)}
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "batches": st.batches, "requests": len(reqs),
+                "memory_waits": st.memory_waits}
 
     arr, reqs = stream(1000.0)
     log("serve warmup")
@@ -372,21 +514,39 @@ def bench_serve(args):
     sat = sorted(sats, key=lambda d: d["rows_per_s"])[1]
     mean_rows = np.mean([r.shape[0] for r in reqs])
     points = {}
-    for frac in (0.25, 0.5, 0.8):
+    for frac in load_fracs:
         qps = frac * sat["rows_per_s"] / mean_rows
         a, r = stream(qps, 1)
         log(f"serve {frac:.0%} load ({qps:.0f} QPS)")
         points[f"{int(frac * 100)}%"] = dict(qps=qps, **serve(a, r))
-    a, r = stream(2000.0, 2)
-    log("serve 2000 QPS")
-    points["2000qps"] = dict(qps=2000.0, **serve(a, r))
+    for qps in fixed_qps:
+        a, r = stream(qps, 2)
+        log(f"serve {qps:.0f} QPS")
+        points[f"{int(qps)}qps"] = dict(qps=qps, **serve(a, r))
+    return {"saturated": sat, "saturated_runs": [d["rows_per_s"] for d in sats], "points": points}
+
+
+def bench_serve(args):
+    import torch
+
+    from paper_1811_00156_amd import rf, synth
+
+    wl = WORKLOADS["c5"]
+    ds = synth.d3()
+    dev = torch.device("cuda:0")
+    codes, binner = rf.aiwc_rf_bin(torch.from_numpy(ds.X).to(dev), torch.from_numpy(ds.device).to(dev),
+                                   ds.n_devices, wl["bins"])
+    forest = rf.aiwc_rf_fit(codes, binner, torch.from_numpy(ds.y).to(dev),
+                            rf.make_params(wl["num_trees"], wl["mtry"], wl["min_node"], True, 1))
+    sv = serve_points(forest, codes.cpu().numpy(), ds.n, args.requests)
     return {
-        "metric": METRIC, "value": sat["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64",
-        "data": "synthetic",
+        "metric": METRIC, "value": sv["saturated"]["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64+f64", "data": "synthetic",
         "config": {"workload": "c5: serving the c3 forest (500 trees, 65 columns); Poisson arrivals, "
-                               "1..4096 rows per request (log-uniform)", "requests": n_req},
-        "saturated": sat, "saturated_rows_per_s_runs": [d["rows_per_s"] for d in sats], "load_points": points,
+                               "1..4096 rows per request (log-uniform)", "requests": args.requests},
+        "saturated": sv["saturated"], "saturated_rows_per_s_runs": sv["saturated_runs"],
+        "load_points": sv["points"],
     }
 
 
@@ -482,6 +642,7 @@ def bench_studies(args):
             rt += train.shape[0] * wl["num_trees"]
         el = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+                               "cpu_model": cpu_model(),
                                "sample": f"{len(sample)} study forests (one leave-one-kernel-out, every {step}th "
                                          f"kernel subset), 505 trees each, {el:.1f} s"}
     return res
@@ -536,6 +697,7 @@ def bench_tune(args):
             rt += ds.n * nt
         el = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": rt / el, "unit": "rows·trees/s", "cores": cores, "kind": "oracle",
+                               "cpu_model": cpu_model(),
                                "sample": f"fit + out-of-bag error of {len(sample)} of the search's triples, {el:.1f} s"}
     return res
 
@@ -563,20 +725,34 @@ def bench_copy(args):
             "config": {"workload": f"copy: {nbytes} bytes read + {nbytes} bytes written per step"}}
 
 
+def bench_lds(args):
+    """The probe's LDS atomic add rates on their own."""
+    peaks = lds_peak()
+    return {"metric": "LDS atomic adds/s (ceiling of the histogram build)", "value": peaks["u64_distinct"],
+            "unit": "adds/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "lds: 8 workgroups of 256 threads per CU, 2000 x 8 adds per lane into a "
+                                   "256-bin histogram per wave"}, "rates": peaks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["copy", "lds"])
     ap.add_argument("--requests", type=int, default=4000)
     ap.add_argument("--repeats", type=int, default=100, help="studies: kernel subsets per kernel count (paper: 500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fixed-shape", action="store_true",
-                    help="no autotuning: grow with AIWC_RF_GROW_BLOCK / AIWC_RF_HUGE_MIN or the defaults")
+    ap.add_argument("--no-lds", action="store_true", help="skip the LDS atomic probe and the lds_roofline object")
+    ap.add_argument("--no-extras", action="store_true", help="c4: skip the c3 roofline and c5 latency legs")
+    ap.add_argument("--tune", action="store_true",
+                    help="let the autotuner pick every fit's launch shape in the warmup (default: the library's "
+                         "default shapes, or AIWC_RF_GROW_BLOCK / AIWC_RF_HUGE_MIN / AIWC_RF_GROW_OCC / "
+                         "AIWC_RF_BIG_COLS)")
     args = ap.parse_args()
-    global FIXED_SHAPE
-    FIXED_SHAPE = args.fixed_shape
+    global TUNE
+    TUNE = args.tune
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(the forest shards by trees across GPUs; only the one-GPU path is built here)"}))
@@ -588,6 +764,8 @@ def main():
         sys.exit(1)
     if args.workload == "copy":
         res = bench_copy(args)
+    elif args.workload == "lds":
+        res = bench_lds(args)
     elif args.workload == "c4":
         res = bench_grid(args)
     elif args.workload == "c5":

@@ -87,3 +87,30 @@ def test_group_and_heldout_argument_checks_without_gpu(lib):
     lib.aiwc_rf_heldout_rows.argtypes = [P, ctypes.c_int32, P, P]
     n = ctypes.c_int32()
     assert lib.aiwc_rf_heldout_rows(None, 0, None, ctypes.byref(n)) == -1
+
+
+PROBE_HEADER = os.path.join(ROOT, "include", "aiwc_rf_probe.h")
+PROBE_LIB = os.path.join(ROOT, "paper_1811_00156_amd", "libaiwc_rf_probe.so")
+
+
+def test_probe_library_exports_its_header():
+    if not os.path.exists(PROBE_LIB):
+        from paper_1811_00156_amd import build
+
+        build.build()
+    plib = ctypes.CDLL(PROBE_LIB)
+    text = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(aiwc_rf_probe_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["aiwc_rf_probe_last_error", "aiwc_rf_probe_lds_add"]
+    for name in names:
+        assert hasattr(plib, name), f"{name} is declared in aiwc_rf_probe.h but not exported"
+    P = ctypes.c_void_p
+    plib.aiwc_rf_probe_lds_add.argtypes = [ctypes.c_int32] * 4 + [P, P, P]
+    plib.aiwc_rf_probe_last_error.restype = ctypes.c_char_p
+    r, ms = ctypes.c_double(), ctypes.c_double()
+    # argument checks fail before any HIP call
+    assert plib.aiwc_rf_probe_lds_add(64, 0, 8, 10, None, None, None) == -1
+    assert plib.aiwc_rf_probe_lds_add(16, 0, 8, 10, ctypes.byref(r), ctypes.byref(ms), None) == -1
+    assert b"width_bits" in plib.aiwc_rf_probe_last_error()
+    assert plib.aiwc_rf_probe_lds_add(64, 2, 8, 10, ctypes.byref(r), ctypes.byref(ms), None) == -1
+    assert plib.aiwc_rf_probe_lds_add(64, 0, 0, 10, ctypes.byref(r), ctypes.byref(ms), None) == -1
