@@ -221,6 +221,19 @@ void aiwc_rf_forest_free(aiwc_rf_forest* forest);
 int aiwc_rf_predict(const aiwc_rf_forest* forest, int32_t forest_index, const uint8_t* codes, int64_t n,
                     double* y_log10_out, void* stream);
 
+/* aiwc_rf_predict for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results as aiwc_rf_predict; the per-row int64 sums live
+ * in a fixed device array of 2^20 entries (8 MiB) that each GPU the library runs
+ * on holds until the process ends, so n <= 2^20 (EINVAL above), and nothing is
+ * allocated or freed.  The forest must live on the current device (EINVAL
+ * otherwise).  Every call on one GPU shares that array, so calls that overlap in
+ * time on one GPU (other threads, or other streams not ordered with this one)
+ * race and may return wrong sums: serialise them.  The array is cleared by the
+ * call's own kernels where needed. */
+int aiwc_rf_predict_noalloc(const aiwc_rf_forest* forest, int32_t forest_index, const uint8_t* codes, int64_t n,
+                            double* y_log10_out, void* stream);
+
 /* Exact partial sums: sum_out[i] = sum over trees [tree_begin, tree_end) of the
  * leaf value reached by row i (int64, units 2^-32).  Sums of disjoint tree ranges
  * add up exactly, so a forest split across devices recombines bit for bit. */

@@ -691,6 +691,27 @@ int aiwc_rf_predict(const aiwc_rf_forest* f, int32_t forest_index, const uint8_t
   });
 }
 
+int aiwc_rf_predict_noalloc(const aiwc_rf_forest* f, int32_t forest_index, const uint8_t* codes, int64_t n,
+                            double* y_log10_out, void* stream) {
+  return guard([&] {
+    check_forest(f, forest_index);
+    require(n >= 0, "n must be >= 0");
+    if (n == 0) return;
+    require(codes && y_log10_out, "null pointer argument");
+    require(n <= kNoAllocPredictRows, "n exceeds the allocation-free limit of 2^20 rows per call");
+    int dev = 0;
+    AIWC_HIP(hipGetDevice(&dev));
+    require(dev == f->device, "the current device is not the forest's device");
+    hipStream_t s = as_stream(stream);
+    const int32_t nt = f->params[forest_index].num_trees;
+    const int64_t t0 = f->first_task[forest_index];
+    require_fitted(f);
+    // the same kernels as aiwc_rf_predict, with the row sums in the fixed array
+    launch_predict(f->nodes.p, f->node_base.p, (int32_t)t0, (int32_t)(t0 + nt), codes, n, f->n_cols,
+                   noalloc_predict_scratch(), y_log10_out, nt, s);
+  });
+}
+
 int aiwc_rf_predict_sum(const aiwc_rf_forest* f, int32_t forest_index, int32_t tree_begin, int32_t tree_end,
                         const uint8_t* codes, int64_t n, int64_t* sum_out, void* stream) {
   return guard([&] {

@@ -313,6 +313,12 @@ void anneal(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binne
             hipStream_t s);
 
 // predict.hip
+// Rows of one allocation-free prediction (aiwc_rf_predict_noalloc): its int64
+// row sums use a fixed device array of this many entries (8 MiB per GPU).
+constexpr int64_t kNoAllocPredictRows = int64_t(1) << 20;
+// That array's address on the current device (looked up once per device with
+// hipGetSymbolAddress, then cached); allocates nothing.
+int64_t* noalloc_predict_scratch();
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                     const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,
                     hipStream_t s);

@@ -7,11 +7,19 @@
 // XCDs while each XCD keeps working on the same trees, so the upper levels of
 // those trees stay in that XCD's L2.  Partial sums of different chunks meet in
 // a 64-bit integer atomic add, which is exact in any order.
+#include <mutex>
+
 #include "device.h"
 #include "internal.h"
 
 namespace aiwc {
 namespace {
+
+// The per-row int64 sums of the allocation-free prediction entry point live in
+// this fixed array, one copy per GPU, held until the process ends.  Host code
+// never uses its name as an address: the address of each device's copy comes
+// from hipGetSymbolAddress (noalloc_predict_scratch).
+__device__ __align__(256) unsigned long long scratch[kNoAllocPredictRows];
 
 constexpr int kPredBlock = 256;
 constexpr int kInterleave = 4;  // trees traversed together per thread to overlap load latency
@@ -113,6 +121,23 @@ void launch_select_device(const uint64_t* nodes, const int64_t* node_base, int32
   const int ab = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (m + 255) / 256));
   k_argmin_devices<<<ab, 256, 0, s>>>(times, m, n_devices, best);
   AIWC_HIP(hipGetLastError());
+}
+
+int64_t* noalloc_predict_scratch() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  AIWC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(AIWC_RF_EINVAL, "device ordinal beyond the allocation-free table");
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    // this device is current: its own copy of the array, at its own address
+    void* p = nullptr;
+    AIWC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  return static_cast<int64_t*>(addr[dev]);
 }
 
 void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,

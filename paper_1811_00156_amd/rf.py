@@ -61,6 +61,7 @@ _sig("aiwc_rf_forest_launch", [_P, _P])
 _sig("aiwc_rf_forest_export_host", [_P, _i32, _i32, _i32, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_forest_free", [_P], None)
 _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
+_sig("aiwc_rf_predict_noalloc", [_P, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_predict_sum", [_P, _i32, _i32, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_select_device", [_P, _i32, _P, _i64, _P, _P, _P])
 _sig("aiwc_rf_oob_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P])
@@ -79,7 +80,8 @@ _sig("aiwc_rf_last_error", [], ctypes.c_char_p)
 SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_host", "aiwc_rf_binner_free",
            "aiwc_rf_fit", "aiwc_rf_forest_wait", "aiwc_rf_forest_info", "aiwc_rf_forest_stats", "aiwc_rf_forest_launch",
            "aiwc_rf_forest_tree_sizes",
-           "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_sum",
+           "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_noalloc",
+           "aiwc_rf_predict_sum",
            "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
            "aiwc_rf_heldout_rows", "aiwc_rf_tune_sa", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
@@ -402,6 +404,18 @@ def aiwc_rf_predict(forest: Forest, codes, forest_index: int = 0, out=None, stre
         out = torch.empty(n, dtype=torch.float64, device=codes.device)
     _check(_L.aiwc_rf_predict(forest.handle, forest_index, _dev(codes, torch.uint8, "codes"), n,
                               _dev(out, torch.float64, "out"), _stream(stream)), "aiwc_rf_predict")
+    return out
+
+
+def aiwc_rf_predict_noalloc(forest: Forest, codes, out, forest_index: int = 0, stream=None):
+    """aiwc_rf_predict without any device allocation (n <= 2^20 rows; out is a
+    caller-owned float64 device tensor).  Overlapping calls on one GPU race."""
+    import torch
+
+    n = codes.shape[0]
+    assert out.shape[0] == n
+    _check(_L.aiwc_rf_predict_noalloc(forest.handle, forest_index, _dev(codes, torch.uint8, "codes"), n,
+                                      _dev(out, torch.float64, "out"), _stream(stream)), "aiwc_rf_predict_noalloc")
     return out
 
 
