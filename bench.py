@@ -358,8 +358,9 @@ def bench_grid(args):
         log(f"grid warmup {i}")
         g, _ = run(rf.FIT_FUSED | tune_flag())
         del g
-        g, _ = run(rf.FIT_PLAIN | tune_flag())
-        del g
+        if not args.no_plain:
+            g, _ = run(rf.FIT_PLAIN | tune_flag())
+            del g
     fused_ms, plain_ms, grow_ms = [], [], []
     for i in range(args.steps):
         g, ms = run(rf.FIT_FUSED | tune_flag())
@@ -370,11 +371,14 @@ def bench_grid(args):
             del g
         else:
             fused = g
+        if args.no_plain:
+            continue
         gp, ms = run(rf.FIT_PLAIN | tune_flag())
         plain_ms.append(ms)
         log(f"grid plain step {i}: {ms:.1f} ms")
         del gp
-    f_ms, p_ms = float(np.median(fused_ms)), float(np.median(plain_ms))
+    f_ms = float(np.median(fused_ms))
+    p_ms = float(np.median(plain_ms)) if plain_ms else float("nan")
     # the kernel's work: per forest (its own mtry in the byte model)
     gbytes = 0
     work = np.zeros(5, np.int64)
@@ -746,6 +750,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lds", action="store_true", help="skip the LDS atomic probe and the lds_roofline object")
     ap.add_argument("--no-extras", action="store_true", help="c4: skip the c3 roofline and c5 latency legs")
+    ap.add_argument("--no-plain", action="store_true", help="c4: skip the per-forest plain launches (profiling runs)")
     ap.add_argument("--tune", action="store_true",
                     help="let the autotuner pick every fit's launch shape in the warmup (default: the library's "
                          "default shapes, or AIWC_RF_GROW_BLOCK / AIWC_RF_HUGE_MIN / AIWC_RF_GROW_OCC / "

@@ -303,3 +303,39 @@ def oob_objective(codes: np.ndarray, n_bins: np.ndarray, y: np.ndarray, seed: in
             out.append((mse, rows))
         return out
     return score
+
+
+def ranking_accuracy(times: np.ndarray, truth: np.ndarray):
+    """How well predicted times rank the devices of each kernel (Sec. VI).
+
+    Sec. VI judges the model as a scheduler would use it: for any pair of devices
+    it should name the one on which the kernel runs faster.  For kernel k and
+    devices i < j the prediction chooses i when times[k, i] <= times[k, j] (the
+    lowest id on a tie, as the device-selection query does) and j otherwise; the
+    choice is correct when its true time is strictly the smaller one.  Pairs whose
+    true times are equal have no wrong choice and are not counted.  The fastest
+    device is hit when the predicted best (the smallest prediction, lowest id on
+    ties) has the smallest true time.
+
+    Returns per kernel (int32 correct pairs, int32 counted pairs, int32 top-1 hit)."""
+    times = np.asarray(times, dtype=np.float64)
+    truth = np.asarray(truth, dtype=np.float64)
+    m, D = times.shape
+    correct = np.zeros(m, np.int32)
+    counted = np.zeros(m, np.int32)
+    hit = np.zeros(m, np.int32)
+    for k in range(m):
+        for i in range(D):
+            for j in range(i + 1, D):
+                if truth[k, i] == truth[k, j]:
+                    continue
+                counted[k] += 1
+                chosen, other = (i, j) if times[k, i] <= times[k, j] else (j, i)
+                if truth[k, chosen] < truth[k, other]:
+                    correct[k] += 1
+        best = 0
+        for d in range(1, D):
+            if times[k, d] < times[k, best]:
+                best = d
+        hit[k] = 1 if truth[k, best] == min(truth[k, d] for d in range(D)) else 0
+    return correct, counted, hit

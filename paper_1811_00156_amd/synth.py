@@ -44,6 +44,9 @@ class Dataset:
     y: np.ndarray  # float64 [n] log10 execution time (seconds)
     kernel: np.ndarray  # int32 [n] index of the (kernel, size) vector the row replicates
     n_devices: int
+    # noiseless log10 time of every (vector, device): the response without its
+    # per-row noise term, the "measured" ordering a device choice is judged by
+    truth: np.ndarray | None = None  # float64 [n_vectors, n_devices]
 
     @property
     def n(self) -> int:
@@ -92,8 +95,9 @@ def generate(n_kernels: int, n_sizes: int, n_devices: int, p_ln: int, p_u: int,
 
     perm = rng.permutation(n)
     X = np.ascontiguousarray(vec[kernel[perm]])
+    truth = np.ascontiguousarray(base[:, None] + dev_off[None, :])
     ds = Dataset(X=X, device=np.ascontiguousarray(device[perm]), y=np.ascontiguousarray(y[perm]),
-                 kernel=np.ascontiguousarray(kernel[perm]), n_devices=n_devices)
+                 kernel=np.ascontiguousarray(kernel[perm]), n_devices=n_devices, truth=truth)
     assert np.all(np.abs(ds.y) <= 64.0), "synthetic response outside the fixed-point range"
     return ds
 
@@ -106,6 +110,17 @@ def d1() -> Dataset:
 def d3() -> Dataset:
     """6250 vectors x 32 devices = 200000 rows, 40 log-normal + 24 uniform features."""
     return generate(6250, 1, 32, 40, 24, 24, SEED_D3)
+
+
+def vector_rows(ds: Dataset) -> np.ndarray:
+    """For every (kernel, size) vector v, one row index of the frame that holds it
+    (the first), so ds.X[vector_rows(ds)[v]] is vector v's features."""
+    first = np.full(int(ds.kernel.max()) + 1, -1, dtype=np.int64)
+    order = np.argsort(ds.kernel, kind="stable")
+    ks = ds.kernel[order]
+    starts = np.r_[0, np.nonzero(np.diff(ks))[0] + 1]
+    first[ks[starts]] = order[starts]
+    return first
 
 
 def small(n_vec: int, n_devices: int, p_ln: int, p_u: int, seed: int, n_pairs: int = 4) -> Dataset:

@@ -239,3 +239,59 @@ def test_anneal_accepts_worse_by_metropolis(oracle):
         assert t["accepted"] == (d <= 0 or u < math.exp(-d / 5.0))
         if t["accepted"]:
             f_cur = float(p[0])
+
+
+# ---------------------------------------------------------------------------- device ranking accuracy (Sec. VI)
+def test_ranking_accuracy_against_kendall_tau(oracle):
+    """Without ties, the share of concordant device pairs is (1 + tau) / 2 for
+    Kendall's tau (scipy), so a dropped pair, a flipped comparison or a wrong
+    index in the pair loop shows."""
+    from scipy.stats import kendalltau
+
+    rng = np.random.default_rng(4)
+    m, D = 40, 15
+    truth = rng.normal(size=(m, D))
+    times = truth + rng.normal(scale=0.7, size=(m, D))
+    correct, counted, hit = oracle.ranking_accuracy(times, truth)
+    assert np.all(counted == D * (D - 1) // 2)
+    for k in range(m):
+        tau = kendalltau(times[k], truth[k]).statistic
+        assert abs(correct[k] / counted[k] - (1.0 + tau) / 2.0) < 1e-12
+        assert hit[k] == int(np.argmin(times[k]) == np.argmin(truth[k]))
+
+
+def test_ranking_accuracy_special_cases(oracle):
+    truth = np.array([[3.0, 1.0, 2.0, 5.0]])
+    # a prediction that is a monotone transform of the truth ranks every pair right
+    c, n, h = oracle.ranking_accuracy(2.0 * truth + 7.0, truth)
+    assert (c[0], n[0], h[0]) == (6, 6, 1)
+    # the reversed ranking ranks every pair wrong and misses the fastest device
+    c, n, h = oracle.ranking_accuracy(-truth, truth)
+    assert (c[0], n[0], h[0]) == (0, 6, 0)
+    # equal true times leave a pair uncounted; a predicted tie chooses the lower id
+    truth = np.array([[1.0, 1.0, 2.0]])
+    times = np.array([[0.5, 0.5, 0.5]])
+    c, n, h = oracle.ranking_accuracy(times, truth)
+    # pairs (0,2) and (1,2) count; the tie picks device 0 (resp. 1), both faster
+    assert (c[0], n[0], h[0]) == (2, 2, 1)
+    times = np.array([[0.7, 0.5, 0.5]])  # (1,2) tie -> device 1 (right); (0,2) picks 2 (wrong)
+    c, n, h = oracle.ranking_accuracy(times, truth)
+    assert (c[0], n[0], h[0]) == (1, 2, 1)
+    # the best is hit when its true time equals the smallest, whichever device that is
+    times = np.array([[0.6, 0.5, 0.9]])
+    assert oracle.ranking_accuracy(times, truth)[2][0] == 1
+
+
+def test_ranking_of_synthetic_truth(oracle):
+    """The generator's noiseless truth ranks its own devices perfectly, and the
+    noisy responses it drew rank most pairs right (the noise is small against
+    the device offsets)."""
+    from paper_1811_00156_amd import synth
+
+    ds = synth.d1()
+    c, n, h = oracle.ranking_accuracy(ds.truth, ds.truth)
+    assert np.all(c == n) and np.all(h == 1)
+    noisy = np.zeros_like(ds.truth)
+    noisy[ds.kernel, ds.device] = ds.y
+    c, n, h = oracle.ranking_accuracy(noisy, ds.truth)
+    assert c.sum() / n.sum() > 0.95
