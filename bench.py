@@ -616,6 +616,21 @@ def bench_studies(args):
         run_study(True)
     torch.cuda.synchronize()
     fit_ms, score_ms, rows_trees, alg1_mae, mae_by_count = run_study(False)
+    # Sec. VI on Algorithm 1's forests (untimed): each forest that never saw kernel
+    # k ranks the devices of k's four size vectors against the noiseless truth
+    f = rf.aiwc_rf_fit_groups(codes, binner, y, [prm] * len(loo), gd, loo, flags=tune_flag())
+    vrows = synth.vector_rows(ds)
+    rc = rn = rh = 0
+    for k in range(37):
+        vecs = np.arange(4 * k, 4 * k + 4)
+        feats = codes[torch.from_numpy(vrows[vecs]).to(dev), :-1].contiguous()
+        _, times = rf.aiwc_rf_select_device(f, feats, forest_index=k, n_devices=ds.n_devices)
+        r = rf.aiwc_rf_rank_accuracy(times, torch.from_numpy(np.ascontiguousarray(ds.truth[vecs])).to(dev))
+        rc += int(r.correct.sum().item())
+        rn += int(r.counted.sum().item())
+        rh += int(r.hit.sum().item())
+    del f
+    log(f"device ranking of unseen kernels: {rc}/{rn} pairs in the right order, fastest device {rh}/148")
     total_ms = fit_ms + score_ms
     n_forests = 37 + int(len(masks))
     res = {
@@ -626,6 +641,8 @@ def bench_studies(args):
                                f"37 leave-one-kernel-out forests + {len(masks)} kernel-subset forests "
                                f"(i = 1..36, {args.repeats} each)", "forests": n_forests},
         "fit_ms": fit_ms, "heldout_scoring_ms": score_ms, "alg1_heldout_mae": alg1_mae,
+        "alg1_device_ranking": {"pairs_right": rc, "pairs_counted": rn, "pairwise_accuracy": rc / max(1, rn),
+                                "fastest_device_hits": rh, "vectors": 148},
         "alg2_mae_by_kernel_count": mae_by_count,
     }
     if not args.no_cpu_baseline:

@@ -343,6 +343,25 @@ int aiwc_rf_tune_sa(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_
 int aiwc_rf_select_device(const aiwc_rf_forest* forest, int32_t forest_index, const uint8_t* feature_codes,
                           int64_t m, double* times_out, int32_t* best_out, void* stream);
 
+/* How well predicted times rank each kernel's devices: the criterion of Sec. VI,
+ * where the model is useful to a scheduler when, for any pair of devices, it
+ * names the one on which the kernel runs faster.
+ *
+ * times, truth: m x n_devices float64 row-major (device): predicted and measured
+ *   (or, for synthetic frames, noiseless) log10 times of each kernel on each
+ *   device, e.g. times_out of aiwc_rf_select_device.
+ * For kernel k and devices i < j the prediction chooses i when times[k,i] <=
+ * times[k,j] (the lowest id on a tie, like aiwc_rf_select_device) and j
+ * otherwise; the choice is right when the chosen device's truth is strictly the
+ * smaller.  Pairs with equal truth have no wrong choice and are not counted.
+ * Outputs (device, m int32 each, any may be NULL): correct_out (pairs chosen
+ * right), counted_out (pairs counted), hit_out (1 when the predicted fastest
+ * device, the smallest prediction with the lowest id on ties, has the smallest
+ * truth).  Only comparisons: exact.  Asynchronous on `stream`.
+ * Errors: EINVAL for m < 0, n_devices outside [1, 256] or null inputs. */
+int aiwc_rf_rank_accuracy(const double* times, const double* truth, int64_t m, int32_t n_devices,
+                          int32_t* correct_out, int32_t* counted_out, int32_t* hit_out, void* stream);
+
 /* ------------------------------------------------------------------------------
  * Serving (the scheduler-facing use of Sec. VI): a resident forest answers a
  * stream of prediction requests of different sizes.  Requests are packed into

@@ -867,4 +867,15 @@ int aiwc_rf_select_device(const aiwc_rf_forest* f, int32_t forest_index, const u
   });
 }
 
+int aiwc_rf_rank_accuracy(const double* times, const double* truth, int64_t m, int32_t n_devices,
+                          int32_t* correct_out, int32_t* counted_out, int32_t* hit_out, void* stream) {
+  return guard([&] {
+    require(m >= 0, "m must be >= 0");
+    require(n_devices >= 1 && n_devices <= 256, "n_devices must be in [1, 256]");
+    if (m == 0) return;
+    require(times && truth, "null pointer argument");
+    launch_rank_accuracy(times, truth, m, n_devices, correct_out, counted_out, hit_out, as_stream(stream));
+  });
+}
+
 }  // extern "C"

@@ -323,6 +323,9 @@ void launch_predict(const uint64_t* nodes, const int64_t* node_base, int32_t tre
                     const uint8_t* codes, int64_t n, int32_t C, int64_t* sum, double* y, int32_t num_trees,
                     hipStream_t s);
 
+void launch_rank_accuracy(const double* times, const double* truth, int64_t m, int32_t D, int32_t* correct,
+                          int32_t* counted, int32_t* hit, hipStream_t s);
+
 void launch_select_device(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                           const uint8_t* feature_codes, int64_t m, int32_t C, int32_t n_devices, int32_t num_trees,
                           uint8_t* expanded, int64_t* sum, double* times, int32_t* best, hipStream_t s);

@@ -108,7 +108,46 @@ __global__ void k_argmin_devices(const double* times, int64_t m, int32_t D, int3
   }
 }
 
+// Sec. VI's scheduler criterion, one thread per kernel: for every device pair
+// i < j the predicted choice is i when times[i] <= times[j] (lowest id on a
+// tie), else j; it is right when the chosen device's true time is strictly the
+// smaller.  Pairs with equal true times are not counted.  The fastest device is
+// hit when the predicted best (smallest prediction, lowest id on ties) has the
+// smallest true time.  Only comparisons: exact.
+__global__ void k_rank_accuracy(const double* times, const double* truth, int64_t m, int32_t D, int32_t* correct,
+                                int32_t* counted, int32_t* hit) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const double* p = times + k * D;
+    const double* t = truth + k * D;
+    int32_t c = 0, n = 0, best = 0;
+    double tmin = t[0];
+    for (int32_t i = 0; i < D; ++i) {
+      const double pi = p[i], ti = t[i];
+      if (pi < p[best]) best = i;
+      tmin = ti < tmin ? ti : tmin;
+      for (int32_t j = i + 1; j < D; ++j) {
+        const double tj = t[j];
+        if (ti == tj) continue;
+        ++n;
+        const bool pick_i = pi <= p[j];
+        c += (pick_i ? ti < tj : tj < ti) ? 1 : 0;
+      }
+    }
+    if (correct) correct[k] = c;
+    if (counted) counted[k] = n;
+    if (hit) hit[k] = t[best] == tmin ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+void launch_rank_accuracy(const double* times, const double* truth, int64_t m, int32_t D, int32_t* correct,
+                          int32_t* counted, int32_t* hit, hipStream_t s) {
+  if (m <= 0) return;
+  const int b = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (m + 255) / 256));
+  k_rank_accuracy<<<b, 256, 0, s>>>(times, truth, m, D, correct, counted, hit);
+  AIWC_HIP(hipGetLastError());
+}
 
 void launch_select_device(const uint64_t* nodes, const int64_t* node_base, int32_t tree_begin, int32_t tree_end,
                           const uint8_t* feature_codes, int64_t m, int32_t C, int32_t n_devices, int32_t num_trees,

@@ -64,6 +64,7 @@ _sig("aiwc_rf_predict", [_P, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_predict_noalloc", [_P, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_predict_sum", [_P, _i32, _i32, _i32, _P, _i64, _P, _P])
 _sig("aiwc_rf_select_device", [_P, _i32, _P, _i64, _P, _P, _P])
+_sig("aiwc_rf_rank_accuracy", [_P, _P, _i64, _i32, _P, _P, _P, _P])
 _sig("aiwc_rf_oob_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P])
 _sig("aiwc_rf_fit_groups", [_P, _i64, _i32, _P, _P, _P, _P, _P, _i32, _u32, _P, _P])
 _sig("aiwc_rf_heldout_error", [_P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P])
@@ -82,7 +83,7 @@ SYMBOLS = ("aiwc_rf_bin", "aiwc_rf_binner_from_counts", "aiwc_rf_binner_export_h
            "aiwc_rf_forest_tree_sizes",
            "aiwc_rf_forest_export_host", "aiwc_rf_forest_free", "aiwc_rf_predict", "aiwc_rf_predict_noalloc",
            "aiwc_rf_predict_sum",
-           "aiwc_rf_select_device", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
+           "aiwc_rf_select_device", "aiwc_rf_rank_accuracy", "aiwc_rf_oob_error", "aiwc_rf_fit_groups", "aiwc_rf_heldout_error",
            "aiwc_rf_heldout_rows", "aiwc_rf_tune_sa", "aiwc_rf_server_create", "aiwc_rf_server_submit", "aiwc_rf_server_poll", "aiwc_rf_server_drain",
            "aiwc_rf_server_stats", "aiwc_rf_server_free", "aiwc_rf_last_error")
 
@@ -484,6 +485,37 @@ def aiwc_rf_select_device(forest: Forest, feature_codes, forest_index: int = 0, 
                                     _dev(times, torch.float64, "times"), _dev(best, torch.int32, "best"),
                                     _stream(stream)), "aiwc_rf_select_device")
     return best, times
+
+
+@dataclass
+class RankAccuracy:
+    correct: object  # int32 device tensor [m]: device pairs ranked right per kernel
+    counted: object  # int32 device tensor [m]: pairs with different true times
+    hit: object  # int32 device tensor [m]: 1 when the predicted fastest device is a truly fastest one
+
+    @property
+    def pairwise(self) -> float:
+        """Share of all counted device pairs, over every kernel, ranked right."""
+        return float(self.correct.sum().item()) / max(1, int(self.counted.sum().item()))
+
+    @property
+    def top1(self) -> float:
+        """Share of kernels whose fastest device was predicted."""
+        return float(self.hit.double().mean().item()) if self.hit.numel() else 0.0
+
+
+def aiwc_rf_rank_accuracy(times, truth, stream=None) -> RankAccuracy:
+    """Sec. VI's pairwise device-ranking accuracy of predicted times (m x D float64
+    device tensor) against true times of the same shape."""
+    import torch
+
+    m, D = times.shape
+    assert tuple(truth.shape) == (m, D)
+    out = [torch.empty(m, dtype=torch.int32, device=times.device) for _ in range(3)]
+    _check(_L.aiwc_rf_rank_accuracy(_dev(times, torch.float64, "times"), _dev(truth, torch.float64, "truth"), m, D,
+                                    *[_dev(o, torch.int32, "out") for o in out], _stream(stream)),
+           "aiwc_rf_rank_accuracy")
+    return RankAccuracy(*out)
 
 
 @dataclass

@@ -129,6 +129,57 @@ def test_select_device_in_grid(rf, oracle, d1b):
     assert np.array_equal(best.cpu().numpy(), ob_best)
 
 
+def test_rank_accuracy_of_unseen_kernels(rf, oracle, d1b):
+    """Sec. VI: forests that never saw kernel k rank the 15 devices of k's four
+    size vectors; pairwise-order counts and fastest-device hits against the
+    generator's noiseless truth equal the oracle's, bit for bit."""
+    ds, ob = d1b
+    g = synth.kernel_groups(ds)
+    held = [0, 11, 36]
+    masks = synth.leave_one_kernel_out_masks()[held]
+    params = [rf.make_params(48, 30, 9, True, 1)] * len(held)
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    forest = rf.aiwc_rf_fit_groups(to_dev(ob.codes), binner, to_dev(ds.y), params, to_dev(g), masks)
+    vrows = synth.vector_rows(ds)
+    total_c = total_n = total_h = 0
+    for f, k in enumerate(held):
+        vecs = np.arange(4 * k, 4 * k + 4)  # kernel k's (kernel, size) vectors
+        feats = np.ascontiguousarray(ob.codes[vrows[vecs], :-1])
+        truth = np.ascontiguousarray(ds.truth[vecs])
+        _, times = rf.aiwc_rf_select_device(forest, to_dev(feats), forest_index=f, n_devices=ds.n_devices)
+        r = rf.aiwc_rf_rank_accuracy(times, to_dev(truth))
+        train = np.nonzero(g != k)[0]
+        of = oracle.fit(ob.codes, ob.n_bins, ds.y, 48, 30, 9, seed=1, train_rows=train)
+        _, o_times = oracle.select_device(of, feats, ds.n_devices)
+        assert np.array_equal(times.cpu().numpy().view(np.uint64), o_times.view(np.uint64))
+        oc, on, oh = oracle.ranking_accuracy(o_times, truth)
+        assert np.array_equal(r.correct.cpu().numpy(), oc)
+        assert np.array_equal(r.counted.cpu().numpy(), on)
+        assert np.array_equal(r.hit.cpu().numpy(), oh)
+        total_c += int(oc.sum())
+        total_n += int(on.sum())
+        total_h += int(oh.sum())
+    log(f"unseen kernels {held}: pairwise order {total_c}/{total_n}, fastest device {total_h}/{4 * len(held)}")
+    assert total_c / total_n > 0.8  # context: the paper reports almost every pair right
+
+
+def test_rank_accuracy_edge_cases(rf, oracle):
+    rng = np.random.default_rng(3)
+    for m, D in ((1, 1), (1, 2), (5, 3), (300, 15), (70, 32)):
+        truth = np.round(rng.normal(size=(m, D)), 1)  # rounded: some equal true times
+        times = np.round(truth + rng.normal(scale=0.3, size=(m, D)), 1)  # and some predicted ties
+        r = rf.aiwc_rf_rank_accuracy(to_dev(times), to_dev(truth))
+        oc, on, oh = oracle.ranking_accuracy(times, truth)
+        assert np.array_equal(r.correct.cpu().numpy(), oc)
+        assert np.array_equal(r.counted.cpu().numpy(), on)
+        assert np.array_equal(r.hit.cpu().numpy(), oh)
+    import torch
+
+    empty = torch.empty((0, 4), dtype=torch.float64, device="cuda:0")
+    r = rf.aiwc_rf_rank_accuracy(empty, empty)
+    assert r.correct.numel() == 0
+
+
 # ---------------------------------------------------------------------------- group studies
 def _group_fit(rf, ob, ds, params, masks):
     g = synth.kernel_groups(ds)
