@@ -141,7 +141,8 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
   }
   launch_init(F->status.p, nullptr, s);
   launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, codes_p, F->status.p, s);
-  const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max);
+  // (sized for the wide phase, which any candidate shape may have)
+  const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max, true);
   hipEvent_t e0, e1;
   AIWC_HIP(hipEventCreate(&e0));
   AIWC_HIP(hipEventCreate(&e1));
@@ -409,12 +410,12 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
 
   GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
   const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
-  const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max);
   bool tuned = false;
   if (flags & AIWC_RF_FIT_TUNE) {
     cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p, d_train.p, queue.p, s);
     tuned = true;
   }
+  const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max, grow_has_wide_phase(cfg));
   aiwc_rf_launch_info& LI = F->launch;
   LI.block = cfg.block;
   LI.waves_per_simd = grow_has_wide_phase(cfg) ? 4 : cfg.occupancy;

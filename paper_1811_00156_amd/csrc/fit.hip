@@ -111,9 +111,13 @@ struct Scratch {
   NodeDesc* big;
   NodeDesc* huge;
   Rec* recs;  // large node j's candidate i at j * mtry + i; wide node h's at (n_big + h) * mtry + i
+  // entry p of a wide node: its row's codes in the node's candidate columns, at
+  // p * cand_stride(mtry) + i (written by the wide batches, read by the partition
+  // instead of the row's code line); null when the launch has no wide phase
+  uint8_t* side;
 };
 
-__host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max) {
+__host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max, bool wide) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> uintptr_t {
     const size_t o = off;
@@ -153,6 +157,7 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->huge = reinterpret_cast<NodeDesc*>(take(sizeof(NodeDesc) * n_large));
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   s->btask = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n_large * (size_t)mtry_max));
+  s->side = wide ? reinterpret_cast<uint8_t*>(take(n * (size_t)cand_stride(mtry_max))) : nullptr;
   return off;
 }
 
@@ -650,6 +655,7 @@ struct Decision {
   bool split;
   uint32_t col, bin, NL;
   int64_t SL;
+  uint32_t cand;  // the split column's position among the node's candidates
 };
 
 // Decide a large or wide node from its per-column records (columns ascending:
@@ -664,10 +670,10 @@ __device__ __forceinline__ Decision decide_from_recs(const Rec* recs, int mtry, 
       bi = i;
     }
   }
-  Decision d{false, 0u, 0u, 0u, 0};
+  Decision d{false, 0u, 0u, 0u, 0, 0u};
   if (bi >= 0 && best - parent_score(S, N) > 0.0) {
     const Rec r = recs[bi];
-    d = Decision{true, r.colbin >> 8, r.colbin & 0xFFu, r.NL, r.SL};
+    d = Decision{true, r.colbin >> 8, r.colbin & 0xFFu, r.NL, r.SL, (uint32_t)bi};
   }
   return d;
 }
@@ -728,6 +734,7 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
   const int mtry = x.T->mtry;
   const int bs = a.bstride;
   const int cst = (mtry + 7) & ~7;
+  const size_t sst = (size_t)cand_stride(mtry);
   const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
   uint64_t* H = reinterpret_cast<uint64_t*>(lds);
   const bool row_regs = a.C <= 80;
@@ -763,6 +770,8 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
         const bool valid = r < sh.wlen[q][j];
         uint64_t v = 0;
         uint32_t row = 0;
+        // this entry's slot of the candidate codes the partition reads back
+        uint8_t* side_row = x.sc.side + (size_t)(sh.wstart[q][j] + r) * sst;
         if (valid) {
           const uint64_t e = x.buf[sh.wstart[q][j] + r];
           const uint32_t w = entry_w(e);
@@ -787,13 +796,19 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
           for (int i0 = 0; i0 < nc; i0 += 8) {
             const uint64_t c8 = *reinterpret_cast<const uint64_t*>(cj + i0);
             const uint32_t lo = rfl((uint32_t)c8), hi = rfl((uint32_t)(c8 >> 32));
+            uint32_t sv0 = 0, sv1 = 0;  // the eight codes, for the partition
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const uint32_t col = ((u < 4 ? lo : hi) >> (8 * (u & 3))) & 0xFFu;
               const uint32_t code = (rw[col >> 2] >> (8 * (col & 3))) & 0xFFu;
+              if (u < 4)
+                sv0 |= code << (8 * u);
+              else
+                sv1 |= code << (8 * (u - 4));
               if (valid && i0 + u < nc)
                 atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)code], (unsigned long long)v);
             }
+            if (valid) *reinterpret_cast<uint2*>(side_row + c0 + i0) = make_uint2(sv0, sv1);
           }
         } else {
           const uint8_t* rp = a.rcodes + (size_t)row * a.rC;
@@ -806,6 +821,9 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
             for (int u = 0; u < 8; ++u)
               if (valid && i0 + u < nc)
                 atomicAdd((unsigned long long*)&Hj[(i0 + u) * bs + (int)cd[u]], (unsigned long long)v);
+            if (valid)
+              *reinterpret_cast<uint2*>(side_row + c0 + i0) =
+                  make_uint2(cd[0] | cd[1] << 8 | cd[2] << 16 | cd[3] << 24, cd[4] | cd[5] << 8 | cd[6] << 16 | cd[7] << 24);
           }
         }
       }
@@ -844,15 +862,16 @@ __device__ __forceinline__ void wide_phase(const Ctx& x, const NodeDesc* list, u
 // the way.  Rows of leaves are not touched again.  Four chunks per wave are in
 // flight at a time, so that their dependent loads (chunk, entry, code)
 // overlap.  `cur` is in LDS or in global memory (inlined once for each).
-template <int BLOCK>
+template <int BLOCK, bool WIDE>
 __device__ __forceinline__ void partition_level(const Ctx& x, uint64_t* __restrict__ out, Cursor* cur,
                                                 uint32_t n_chunks) {
   constexpr int NW = BLOCK / kWave;
   constexpr int UP = 4;
   const GrowArgs& a = *x.a;
   const int lane = (int)lane_id();
+  const size_t sst = (size_t)cand_stride(x.T->mtry);
   for (uint32_t c0 = threadIdx.x / kWave; c0 < n_chunks; c0 += UP * NW) {
-    uint32_t rk[UP], col[UP], bin[UP];
+    uint32_t rk[UP], col[UP], bin[UP], sci[UP], pos[UP];
     uint64_t e[UP];
     bool mv[UP], go_left[UP];
 #pragma unroll
@@ -862,14 +881,26 @@ __device__ __forceinline__ void partition_level(const Ctx& x, uint64_t* __restri
       const uint32_t p0 = rfl(cw.x), en = rfl(cw.y), cb = rfl(cw.w);
       rk[u] = rfl(cw.z);
       col[u] = cb & 0xFFu;
-      bin[u] = cb >> 8;
-      const uint32_t p = p0 + (uint32_t)lane;
-      mv[u] = p < en;
-      e[u] = mv[u] ? x.buf[p] : 0ull;
+      bin[u] = (cb >> 8) & 0xFFu;
+      sci[u] = cb >> 16;
+      pos[u] = p0 + (uint32_t)lane;
+      mv[u] = pos[u] < en;
+      e[u] = mv[u] ? x.buf[pos[u]] : 0ull;
     }
+    // the split column's code: beside the entry when a wide batch searched the
+    // node (candidate index + 1 in the chunk word), else from the row's codes
 #pragma unroll
-    for (int u = 0; u < UP; ++u)
-      go_left[u] = mv[u] && a.rcodes[(size_t)entry_row(e[u]) * a.rC + col[u]] <= bin[u];
+    for (int u = 0; u < UP; ++u) {
+      uint32_t code = 0;
+      if (mv[u]) {
+        if constexpr (WIDE)
+          code = sci[u] ? x.sc.side[(size_t)pos[u] * sst + (sci[u] - 1u)]
+                        : a.rcodes[(size_t)entry_row(e[u]) * a.rC + col[u]];
+        else
+          code = a.rcodes[(size_t)entry_row(e[u]) * a.rC + col[u]];
+      }
+      go_left[u] = mv[u] && code <= bin[u];
+    }
 #pragma unroll
     for (int u = 0; u < UP; ++u) {
       if (c0 + (uint32_t)(u * NW) >= n_chunks) break;
@@ -1094,13 +1125,17 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
       const uint32_t k = b0 + tid;
       const bool in = k < level_cnt;
       uint8_t stk = in ? sc.status[k] : kLeaf;
-      Decision dc{false, 0u, 0u, 0u, 0};
+      Decision dc{false, 0u, 0u, 0u, 0, 0u};
+      // a wide node's rows carry their candidate codes (candidate index + 1 in
+      // the partition's chunk word; 0 = read the row's code)
+      uint32_t side_ci = 0;
       if (stk == kBig || stk == kHuge) {
         const uint32_t ri = sc.ridx[k] + (stk == kHuge ? n_big : 0u);
         dc = decide_from_recs(sc.recs + (size_t)ri * mtry, mtry, x.mS[k], x.mN[k]);
+        if (WIDE && stk == kHuge) side_ci = dc.cand + 1u;
         stk = dc.split ? kSplit : kLeaf;
       } else if (stk == kSplitDone) {
-        dc = Decision{true, sc.dcol[k], sc.dbin[k], sc.dNL[k], sc.dSL[k]};
+        dc = Decision{true, sc.dcol[k], sc.dbin[k], sc.dNL[k], sc.dSL[k], 0u};
       }
       const bool split = stk == kSplit || stk == kSplitDone;
       // (the small nodes' rows were placed by their searches)
@@ -1114,7 +1149,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
       // (the bounds below hold by construction; the guards keep a broken
       // invariant from writing outside the scratch arrays)
       if (nch > 0 && (uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2)) {
-        const uint32_t st = x.mstart[k], en = x.mend[k], cb = dc.col | (dc.bin << 8);
+        const uint32_t st = x.mstart[k], en = x.mend[k], cb = dc.col | (dc.bin << 8) | (side_ci << 16);
         for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint4(st + c * kWave, en, r, cb);
       }
       if (in) {
@@ -1174,9 +1209,9 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     }
     // (f) partition the entries of split nodes into their children's segments
     if (lds_cur)
-      partition_level<BLOCK>(x, X.buf, lcur, n_chunks);
+      partition_level<BLOCK, WIDE>(x, X.buf, lcur, n_chunks);
     else
-      partition_level<BLOCK>(x, X.buf, sc.cur, n_chunks);
+      partition_level<BLOCK, WIDE>(x, X.buf, sc.cur, n_chunks);
     __syncthreads();
     // (g) the boundary between each pair of children, and their sums of w y^2
     for (uint32_t r = tid; r < n_split; r += BLOCK) {
@@ -1224,7 +1259,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) vo
   // and let the fit report EINVAL
   if (__atomic_load_n(a.status, __ATOMIC_RELAXED) & kStatusBadCode) return;
   Scratch sc;
-  carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max);
+  carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max, WIDE);
   for (int c = threadIdx.x; c < a.C; c += BLOCK) sh.nbins[c] = (uint16_t)a.n_bins[c];
   for (;;) {
     if (threadIdx.x == 0) sh.task = atomicAdd(a.queue, 1u);
@@ -1350,9 +1385,9 @@ void launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   AIWC_HIP(hipGetLastError());
 }
 
-size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max) {
+size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide) {
   Scratch s;
-  return carve(&s, 0, n_cap, mtry_max);
+  return carve(&s, 0, n_cap, mtry_max, wide);
 }
 
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
@@ -1401,7 +1436,7 @@ GrowArgs grow_args(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const 
   a.n_cap = g.n_cap;
   a.mtry_max = mtry_max;
   a.huge_min = cfg.huge_min;
-  a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max);
+  a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max, grow_has_wide_phase(cfg));
   const Layout L = grow_layout(cfg, mtry_max, C);
   a.union_bytes = L.union_bytes;
   a.wave_bytes = L.wave_bytes;

@@ -257,7 +257,9 @@ inline int32_t padded_cols(int32_t C) {
 }
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
                     int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s);
-size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max);
+// Scratch of one grow workgroup (wide: the launch has the wide phase, whose
+// rows also keep their candidate codes for the partition).
+size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide);
 int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
 // The buffers of one grow launch: the codes (dense and row-padded), the
 // training-row lists, the tasks and everything the trees write.
