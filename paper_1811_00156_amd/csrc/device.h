@@ -214,6 +214,30 @@ __device__ __forceinline__ ArgMax wave_argmax(double score, int32_t key) {
   return r;
 }
 
+// The same when lane order is key order (lane l's key below lane l+1's): a wave
+// max of the scores with the scan's DPP pattern, then the lowest lane that holds
+// it.  Scores must not be NaN.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double max_step(double m) {
+  constexpr uint64_t kMinusInf = 0xFFF0000000000000ull;
+  const double o = __builtin_bit_cast(double, dpp64<CTRL, ROW_MASK>(kMinusInf, __builtin_bit_cast(uint64_t, m)));
+  return o > m ? o : m;
+}
+__device__ __forceinline__ ArgMax wave_argmax_lane_ordered(double score, int32_t key) {
+  double m = score;
+  m = max_step<kDppRowShr1, 0xf>(m);
+  m = max_step<kDppRowShr2, 0xf>(m);
+  m = max_step<kDppRowShr4, 0xf>(m);
+  m = max_step<kDppRowShr8, 0xf>(m);
+  m = max_step<kDppRowBcast15, 0xa>(m);
+  m = max_step<kDppRowBcast31, 0xc>(m);
+  ArgMax r;
+  r.score = __builtin_bit_cast(double, read_lane(__builtin_bit_cast(uint64_t, m), kWave - 1));
+  r.lane = __builtin_ctzll(__ballot(score == r.score));
+  r.key = read_lane(key, r.lane);
+  return r;
+}
+
 // All-reductions inside aligned segments of W = 4, 8, 16 or 32 lanes, for an
 // operation that is associative and commutative.  Within a row of 16 the steps
 // are DPP permutations (every source lane valid): a rotation by 8 pairs lanes

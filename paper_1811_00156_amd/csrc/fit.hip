@@ -581,7 +581,9 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
       }
     }
   }
-  return wave_argmax(lbest, lbin);
+  // lane l's bins precede lane l+1's: the lowest lane with the best score holds
+  // the lowest best bin
+  return wave_argmax_lane_ordered(lbest, lbin);
 }
 
 // Large nodes: one wave per (node, up to four consecutive candidate columns),
