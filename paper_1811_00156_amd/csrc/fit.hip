@@ -456,10 +456,12 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
 }
 
 // Nodes of 33..64 rows: one node per wave, one row per lane.  Per candidate
-// column the rows' packed (w, w y) are added into LDS bins of the codes that
-// occur, the occurring codes are ranked through a 256-bit presence mask, and a
-// wave prefix scan over the ranked codes gives the left sums of every split
-// (cost independent of the bin count and of the number of rows).
+// column the rows' packed (w, w y) are added into the column's LDS bins, a wave
+// prefix scan over the bins (ceil(B / 64) per lane) turns them into left sums,
+// and every lane scores the split at its own row's code (rows with the largest
+// code leave the right side empty and are skipped; lanes sharing a code score
+// the same split).  Two bin buffers alternate between candidates, so that the
+// previous candidate's bins are cleared while this one is scanned.
 __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
@@ -477,62 +479,69 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   const uint8_t* rowp = a.rcodes + (size_t)entry_row(e) * a.rC;
   const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
-  uint64_t* hv = reinterpret_cast<uint64_t*>(area);            // [256] packed bins by code
-  uint32_t* mask = reinterpret_cast<uint32_t*>(area + 2048);   // [8]
-  uint64_t* dV = reinterpret_cast<uint64_t*>(area + 2112);     // [64] bins by rank
-  uint32_t* dC = reinterpret_cast<uint32_t*>(area + 2624);     // [64] codes by rank
-  uint8_t* s_cand = area + 2880;                               // [mtry]
+  uint64_t* hb = reinterpret_cast<uint64_t*>(area);  // [2][256] packed bins, then prefix sums
+  uint8_t* s_cand = area + 4096;                     // [mtry]
   for (int i = lane; i < mtry; i += kWave) s_cand[i] = cand[i];
+  // both buffers start zeroed: four bins per lane each
+  *reinterpret_cast<uint4*>(hb + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+  *reinterpret_cast<uint4*>(hb + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
+  *reinterpret_cast<uint4*>(hb + 256 + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+  *reinterpret_cast<uint4*>(hb + 256 + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
   wave_lds_sync();
 
-  // each lane keeps the best of the splits it scores (rank `lane` of every
-  // candidate) as (score, candidate index << 8 | bin); one arg-max at the end
+  // each lane keeps the best of the splits it scores (the one at its own code,
+  // for every candidate) as (score, candidate index << 8 | bin); one arg-max at
+  // the end
   double best = -1.0;
   int32_t best_ib = INT_MAX;
   uint32_t c_next = rfl(s_cand[0]);
   uint32_t code_next = valid ? rowp[c_next] : 0u;
   for (int i = 0; i < mtry; ++i) {
     const uint32_t code = code_next;
+    const uint32_t B = (uint32_t)a.n_bins[c_next];  // this candidate column's bins
     if (i + 1 < mtry) {  // fetch the next column's codes while this one is scanned
       c_next = rfl(s_cand[i + 1]);
       code_next = valid ? rowp[c_next] : 0u;
     }
-    if (valid) hv[code] = 0;
-    if (lane < 8) mask[lane] = 0;
+    uint64_t* hv = hb + (i & 1) * 256;
+    if (valid) atomicAdd((unsigned long long*)&hv[code], (unsigned long long)pv);
     wave_lds_sync();
-    if (valid) {
-      atomicAdd((unsigned long long*)&hv[code], (unsigned long long)pv);
-      atomicOr(&mask[code >> 5], 1u << (code & 31));
+    // the previous candidate's buffer is free again (every lane read its left
+    // sums before these adds): clear it while this one is scanned
+    if (i > 0) {
+      uint64_t* ho = hb + ((i - 1) & 1) * 256;
+      *reinterpret_cast<uint4*>(ho + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(ho + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
     }
-    wave_lds_sync();
-    uint32_t below = 0, total = 0;
+    // inclusive prefix sums of the B bins, ceil(B / 64) consecutive bins per lane
+    const int q = ((int)B + kWave - 1) / kWave;
+    const int b0 = lane * q;
+    uint64_t h[4];
+    uint64_t loc = 0;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const uint32_t word = mask[m];
-      const uint32_t cnt = (uint32_t)__popc(word);
-      below += ((uint32_t)m < (code >> 5)) ? cnt : 0u;
-      total += cnt;
+    for (int u = 0; u < 4; ++u) {
+      h[u] = u < q && b0 + u < (int)B ? hv[b0 + u] : 0ull;
+      loc += h[u];
     }
-    below += (uint32_t)__popc(mask[code >> 5] & ((1u << (code & 31)) - 1u));
-    if (valid) {
-      dV[below] = hv[code];
-      dC[below] = code;
+    uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v += h[u];
+      if (u < q && b0 + u < (int)B) hv[b0 + u] = v;
     }
     wave_lds_sync();
-    const bool have = (uint32_t)lane < total;
-    const uint64_t v_i = have ? dV[lane] : 0ull;
-    const uint32_t bin = have ? dC[lane] : 0xFFFFu;
-    const uint64_t V = wave_incl_scan<uint64_t>(v_i);
-    const uint32_t NL = packed_n(V);
-    const int64_t SL = packed_s(V, NL);
-    if ((uint32_t)lane + 1 < total) {
-      const double sc = split_score(SL, NL, S - SL, N - NL);
-      if (sc > best) {
-        best = sc;
-        best_ib = (i << 8) | (int32_t)bin;
+    if (valid) {
+      const uint64_t V = hv[code];
+      const uint32_t NL = packed_n(V);
+      if (NL < N) {
+        const int64_t SL = packed_s(V, NL);
+        const double sc = split_score(SL, NL, S - SL, N - NL);
+        if (sc > best) {
+          best = sc;
+          best_ib = (i << 8) | (int32_t)code;
+        }
       }
     }
-    wave_lds_sync();
   }
   const ArgMax am = wave_argmax(best, best_ib);
   const bool split = am.score >= 0.0 && am.score - parent_score(S, N) > 0.0;
@@ -1330,8 +1339,8 @@ Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   L.bstride = (std::max(cfg.bins_max, 1) + 63) / 64 * 64;
   L.big_stride = (std::max(cfg.bins_max, 1) + 3) / 4 * 4;
   // a wave's histogram, or the staging of its small-node task (the rank task's
-  // bins and candidates take 2880 + mtry bytes)
-  const size_t wb = std::max(sizeof(WaveHist), (size_t)2880 + (size_t)mtry_max);
+  // two bin buffers and candidates take 4096 + mtry bytes)
+  const size_t wb = std::max(sizeof(WaveHist), (size_t)4096 + (size_t)mtry_max);
   L.wave_bytes = (uint32_t)((wb + 255) / 256 * 256);
   L.big_cols = (int32_t)std::min<size_t>(4, L.wave_bytes / (8 * (size_t)L.big_stride));
   const size_t waves = (size_t)(cfg.block / kWave) * L.wave_bytes;
