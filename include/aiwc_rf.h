@@ -140,7 +140,10 @@ void aiwc_rf_binner_free(aiwc_rf_binner* binner);
                                 AIWC_RF_HUGE_MIN (rows above which a node is searched by the
                                 whole workgroup), AIWC_RF_GROW_OCC (4, 5 or 6 waves per SIMD),
                                 AIWC_RF_GROW_WG_PER_CU and AIWC_RF_BIG_COLS (1 to 4 columns per
-                                large-node task) override it, again without changing results */
+                                large-node task) override it, again without changing results;
+                                AIWC_RF_WIDE_SUMS=1 makes the small-node searches always add
+                                64-bit sums (otherwise only when a bootstrap weight exceeds
+                                255), also without changing results */
 int aiwc_rf_fit(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner,
                 const double* y_log10, const int8_t* fold_id, const aiwc_rf_params* params_host,
                 const int32_t* heldout_fold_host, int32_t n_forests, uint32_t flags, aiwc_rf_forest** forest,

@@ -73,6 +73,7 @@ GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t
   if (const char* e = std::getenv("AIWC_RF_HUGE_MIN")) cfg.huge_min = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_GROW_OCC")) cfg.occupancy = std::atoi(e);
   if (const char* e = std::getenv("AIWC_RF_BIG_COLS")) cfg.big_cols = std::atoi(e);
+  if (const char* e = std::getenv("AIWC_RF_WIDE_SUMS")) cfg.wide_sums = std::atoi(e) != 0;
   return cfg;
 }
 

@@ -194,6 +194,7 @@ struct GrowArgs {
   int64_t n_cap;
   int32_t mtry_max;
   int32_t huge_min;  // nodes with more rows than this are searched in workgroup-wide batches
+  int32_t wide_sums;  // 1: the small-node searches add 64-bit sums even when weights fit a byte
   int32_t bstride;   // bins per column histogram in the workgroup-wide layout
   int32_t big_cols;    // candidate columns per large-node task (1 .. 4)
   int32_t big_stride;  // bins per column histogram of a large-node task
@@ -398,9 +399,27 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   const int64_t y = entry_y(e);
   const int64_t wy = (int64_t)w * y;
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
-  uint64_t* s_pv = reinterpret_cast<uint64_t*>(area);  // [64] packed (w, w y)
-  uint8_t* s_codes = area + 512;                       // [64 columns][64 lanes]
-  s_pv[lane] = pack_ns(w, wy);
+  uint8_t* s_codes = area + 512;  // [64 columns][64 lanes]
+  // The rows' weights and w y, staged in the first 512 bytes.  When every weight
+  // of the wave fits a byte (bootstrap multiplicities nearly always do), as byte
+  // planes: the group of rows 4j..4j+3 takes 32 bytes, word 0 their weights and
+  // words 1..4 bytes 0..3 of their w y (|w y| < 2^30: two's complement, the top
+  // byte signed), so that four rows' left sums are five 4-byte dot products.
+  // Otherwise packed (w, w y) words, one per row.
+  const bool bytes_ok = !a.wide_sums && __ballot(w > 255u) == 0ull;
+  uint8_t* planes = area;
+  uint64_t* s_pv = reinterpret_cast<uint64_t*>(area);
+  if (bytes_ok) {
+    const uint32_t wy32 = (uint32_t)(int32_t)wy;
+    uint8_t* gp = planes + (lane >> 2) * 32 + (lane & 3);
+    gp[0] = (uint8_t)w;
+    gp[4] = (uint8_t)wy32;
+    gp[8] = (uint8_t)(wy32 >> 8);
+    gp[12] = (uint8_t)(wy32 >> 16);
+    gp[16] = (uint8_t)(wy32 >> 24);
+  } else {
+    s_pv[lane] = pack_ns(w, wy);
+  }
   const uint8_t* rowp = a.rcodes + (size_t)row * a.rC;
   const uint8_t* cand = x.sc.cand + (size_t)k * cand_stride(mtry);
 
@@ -409,6 +428,7 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   double best = -1.0;
   uint32_t best_ib = 0xFFFFFFFFu;  // candidate index << 8 | bin
   const uint64_t* seg_pv = s_pv + sbase;
+  const uint8_t* seg_planes = planes + (sbase >> 2) * 32;
   for (int i0 = 0; i0 < mtry; i0 += kWave) {
     const int nc = min(kWave, mtry - i0);
     // gather the row's codes in every candidate column of this chunk at once:
@@ -428,16 +448,44 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
       const uint8_t* col_codes = s_codes + i * kWave;
       const uint32_t code = col_codes[lane];
       const uint32_t* seg_codes = reinterpret_cast<const uint32_t*>(col_codes + sbase);
-      uint64_t acc = 0;  // packed left sums of the split at this lane's code
+      // left sums of the split at this lane's code: the segment's rows with a code <= it
+      uint32_t NL;
+      int64_t SL;
+      if (bytes_ok) {
+        // four rows at a time: byte b of `ind` is 1 when row b's code is <= this
+        // lane's (per 16-bit half, 256 + code - c stays in [1, 511], so its bit 8
+        // is the comparison and no borrow crosses the halves), then dot products
+        // with the weight and w y byte planes
+        const uint32_t kk = code * 0x00010001u + 0x01000100u;
+        uint32_t aN = 0, a0 = 0, a1 = 0, a2 = 0;
+        int32_t a3 = 0;
 #pragma unroll 2
-      for (int b4 = 0; b4 < W / 4; ++b4) {
-        const uint32_t c4 = seg_codes[b4];
+        for (int b4 = 0; b4 < W / 4; ++b4) {
+          const uint32_t c4 = seg_codes[b4];
+          const uint32_t ind = (((kk - (c4 & 0x00FF00FFu)) >> 8) & 0x00010001u) |
+                               ((kk - ((c4 >> 8) & 0x00FF00FFu)) & 0x01000100u);
+          const uint4 pl = *reinterpret_cast<const uint4*>(seg_planes + b4 * 32);
+          const uint32_t p3 = *reinterpret_cast<const uint32_t*>(seg_planes + b4 * 32 + 16);
+          aN = __builtin_amdgcn_udot4(ind, pl.x, aN, false);
+          a0 = __builtin_amdgcn_udot4(ind, pl.y, a0, false);
+          a1 = __builtin_amdgcn_udot4(ind, pl.z, a1, false);
+          a2 = __builtin_amdgcn_udot4(ind, pl.w, a2, false);
+          a3 = __builtin_amdgcn_sdot4((int32_t)ind, (int32_t)p3, a3, false);
+        }
+        NL = aN;
+        SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)a2 << 16) + ((int64_t)a3 << 24);
+      } else {
+        uint64_t acc = 0;  // packed left sums
+#pragma unroll 2
+        for (int b4 = 0; b4 < W / 4; ++b4) {
+          const uint32_t c4 = seg_codes[b4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += ((c4 >> (8 * u)) & 0xFFu) <= code ? seg_pv[4 * b4 + u] : 0ull;
+          for (int u = 0; u < 4; ++u) acc += ((c4 >> (8 * u)) & 0xFFu) <= code ? seg_pv[4 * b4 + u] : 0ull;
+        }
+        NL = packed_n(acc);
+        SL = packed_s(acc, NL);
       }
-      const uint32_t NL = packed_n(acc);
       if (valid && NL < N) {
-        const int64_t SL = packed_s(acc, NL);
         const double sc = split_score(SL, NL, S - SL, N - NL);
         if (sc > best) {
           best = sc;
@@ -1447,6 +1495,7 @@ GrowArgs grow_args(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const 
   a.n_cap = g.n_cap;
   a.mtry_max = mtry_max;
   a.huge_min = cfg.huge_min;
+  a.wide_sums = cfg.wide_sums ? 1 : 0;
   a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max, grow_has_wide_phase(cfg));
   const Layout L = grow_layout(cfg, mtry_max, C);
   a.union_bytes = L.union_bytes;

@@ -215,6 +215,7 @@ struct GrowConfig {
   int occupancy = 4;     // waves per SIMD the kernel without the wide phase is built for (4, 5 or 6)
   int big_cols = 0;      // candidate columns per large-node task, at most what the wave area holds (0 = all it holds)
   int huge_min = 4096;   // nodes with more in-bag rows are searched in workgroup-wide batches
+  bool wide_sums = false;  // small-node searches always add 64-bit sums (no byte-plane dot products)
   int wide_bytes = 0;    // LDS of a wide batch's histograms (0: 128 bytes per thread)
   int bins_max = 256;    // largest bin count of any column
   int64_t n_cap = 0;     // largest training set of any tree

@@ -222,3 +222,24 @@ def test_line_aligned_code_rows(p_ln, p_u, n_vec, huge_min):
                  params=rf.make_params(2, 20, 2, True, 14))
     for t, tree in enumerate(f.export()):
         assert_tree_equal(tree, of.tree(t), f"line-aligned rows huge_min {huge_min} tree {t}")
+
+
+@pytest.mark.parametrize("wide_sums", ["0", "1"])
+@pytest.mark.parametrize("block,occ", [("192", "6"), ("512", "4")])
+def test_small_node_sums_byte_planes_and_64_bit(setup, wide_sums, block, occ):
+    """The small-node searches' left sums from byte-plane dot products (weights
+    below 256) and from 64-bit adds (forced) grow the same trees; no-bootstrap
+    and bootstrap forests, with 64-row leaves so that every segment width occurs."""
+    rf, ds, ob, of = setup
+    env = {"AIWC_RF_WIDE_SUMS": wide_sums, "AIWC_RF_GROW_BLOCK": block, "AIWC_RF_GROW_OCC": occ,
+           "AIWC_RF_HUGE_MIN": "100000"}
+    log(f"small-node sums wide_sums={wide_sums} block={block}")
+    f = fit_with(rf, ds, ob, env)
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"wide_sums {wide_sums} tree {t}")
+    from oracle import oracle as O
+
+    ofn = O.fit(ob.codes, ob.n_bins, ds.y, 3, 7, 1, seed=4, bootstrap=False)
+    g = fit_with(rf, ds, ob, env, params=rf.make_params(3, 7, 1, False, 4))
+    for t, tree in enumerate(g.export()):
+        assert_tree_equal(tree, ofn.tree(t), f"wide_sums {wide_sums} no bootstrap tree {t}")
