@@ -48,16 +48,18 @@ int32_t status_to_code(uint32_t st, std::string& msg) {
 
 GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t>& n_bins) {
   GrowConfig cfg;
-  // large training sets: 512 threads per tree, every node above 64 rows in
-  // workgroup-wide batches; small ones: 512 threads per tree while trees are
-  // few, and once there are enough trees to fill several workgroups per CU,
-  // 192 threads at 6 waves per SIMD (eight resident trees per CU).  A
-  // large-node task takes two candidate columns while trees are few (more
-  // tasks per node for the tree's waves), up to four once the CUs are full.
+  // large training sets: 1024 threads per tree, nodes above 512 rows in
+  // workgroup-wide batches (the autotuner's choice on 200000 rows, 2 % ahead
+  // of 512 threads with every node above 64 rows in batches); small ones: 512
+  // threads per tree while trees are few, and once there are enough trees to
+  // fill several workgroups per CU, 192 threads at 6 waves per SIMD (eight
+  // resident trees per CU).  A large-node task takes two candidate columns
+  // while trees are few (more tasks per node for the tree's waves), up to four
+  // once the CUs are full.
   cfg.big_cols = 2;
   if (n_cap > 16384) {
-    cfg.block = 512;
-    cfg.huge_min = 64;
+    cfg.block = 1024;
+    cfg.huge_min = 512;
   } else if (n_tasks >= 4LL * device_info().cus) {
     cfg.block = 192;
     cfg.occupancy = 6;

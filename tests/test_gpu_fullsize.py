@@ -71,7 +71,7 @@ def test_c3_every_tree_and_predictions(rf, c3, tuned):
     log(f"c3 launch shape {li}")
     assert li["wide_phase"] == 1
     if not tuned:
-        assert li["block"] == 512 and li["wide_limit"] == 64
+        assert li["block"] == 1024 and li["wide_limit"] == 512
     compare_forest(forest, of, C3["num_trees"], f"C3 ({'tuned' if tuned else 'default'} shape)")
     pc = to_dev(c3["pool_codes"])
     g = rf.aiwc_rf_predict(forest, pc).cpu().numpy()
