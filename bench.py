@@ -95,8 +95,9 @@ def grow_bytes(work, mtry):
     return searched_rows * (mtry + 13) + part_rows * 10
 
 
-TRAFFIC_SOURCES = ["paper_1811_00156_amd/csrc/fit.hip", "paper_1811_00156_amd/csrc/device.h",
-                   "paper_1811_00156_amd/csrc/api.cpp", "paper_1811_00156_amd/csrc/internal.h"]
+TRAFFIC_SOURCES = ["paper_1811_00156_amd/csrc/fit.hip", "paper_1811_00156_amd/csrc/fit_grouped.hip",
+                   "paper_1811_00156_amd/csrc/device.h", "paper_1811_00156_amd/csrc/api.cpp",
+                   "paper_1811_00156_amd/csrc/internal.h"]
 
 
 def measured_traffic(kernel_key):
@@ -112,8 +113,10 @@ def measured_traffic(kernel_key):
     rec = json.load(open(path)).get(kernel_key)
     if not rec:
         return None
+    if rec.get("kernel_sources") != TRAFFIC_SOURCES:
+        return None
     h = hashlib.sha256()
-    for src in rec["kernel_sources"]:
+    for src in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest()[:16] != rec["kernel_sha256_16"]:
         return None

@@ -175,7 +175,10 @@ int aiwc_rf_forest_info(const aiwc_rf_forest* forest, int32_t forest_index, int3
  * split was searched, the number of such nodes, the in-bag rows of every node that
  * split (rows moved to children), (max over trees) the number of levels grown, and
  * the rows added to LDS histogram bins (in-bag rows x mtry of every searched node
- * above 32 rows: one LDS atomic add each).
+ * above 32 rows: one LDS atomic add each).  The counts are of the work done: in a
+ * fused fit, trees that differ only in min.node.size are grown once down to the
+ * level where they part (task groups, see aiwc_rf_launch_info), and the shared
+ * levels count for the group's tree with the smallest min.node.size.
  * grow_ms_host receives the device time of the call's tree-growing launch(es),
  * from events recorded on the fit stream around them (for a grid: the whole call).
  * Either output may be NULL.  Waits for an ASYNC fit. */
@@ -193,6 +196,10 @@ typedef struct {
   int32_t graph;          /* 1 when the fit ran as one executable-graph launch (fused grid) */
   int32_t graph_reused;   /* 1 when that graph was built by an earlier fit of the same shape */
   int32_t tuned;          /* 1 when the shape came from the autotuner (timed now or cached) */
+  int32_t task_groups;    /* work items of the grow launch(es): a fused fit grows tree t of the
+                             forests that differ only in min.node.size (up to 8 of them) as one
+                             group, sharing the levels above the first one holding a node that is
+                             a leaf for some of them only; otherwise every tree is its own item */
 } aiwc_rf_launch_info;
 int aiwc_rf_forest_launch(const aiwc_rf_forest* forest, aiwc_rf_launch_info* info_host);
 

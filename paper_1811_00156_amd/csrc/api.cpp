@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <set>
+#include <tuple>
 
 #include "device.h"
 #include "internal.h"
@@ -145,7 +146,7 @@ GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, a
   launch_init(F->status.p, nullptr, s);
   launch_prepare(codes, n, n_cols, binner->d_n_bins.p, y, y_fp, codes_p, F->status.p, s);
   // (sized for the wide phase, which any candidate shape may have)
-  const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max, true);
+  const size_t per_wg = grow_scratch_bytes(base.n_cap, mtry_max, true, false);
   hipEvent_t e0, e1;
   AIWC_HIP(hipEventCreate(&e0));
   AIWC_HIP(hipEventCreate(&e1));
@@ -329,6 +330,45 @@ void check_fit_args(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_
   require(total_trees <= (int64_t)INT32_MAX, "too many trees in one call");
 }
 
+// Task groups of a fused fit: tree t of every forest that differs from others
+// only in min.node.size (same training rows, mtry, bootstrap, seed and tree
+// count), by min.node.size ascending, at most kGroupMax to a group; the grow
+// kernel grows a group's trees once down to the level where they part.  The
+// groups of the costliest forests (training rows x mtry) come first in the
+// queue, so that the cheapest ones fill the launch's tail.
+void make_task_groups(const aiwc_rf_params* P, int32_t n_forests, const RowLists& L,
+                      const std::vector<int64_t>& first_task, std::vector<int32_t>& member,
+                      std::vector<int32_t>& first) {
+  using Key = std::tuple<int64_t, int32_t, int32_t, int32_t, uint64_t, int32_t>;
+  std::map<Key, std::vector<int32_t>> sets;
+  std::vector<Key> order;
+  for (int32_t f = 0; f < n_forests; ++f) {
+    const Key k{L.train[f].first, L.train[f].second, P[f].mtry, P[f].bootstrap, P[f].seed, P[f].num_trees};
+    auto it = sets.find(k);
+    if (it == sets.end()) {
+      order.push_back(k);
+      it = sets.emplace(k, std::vector<int32_t>()).first;
+    }
+    it->second.push_back(f);
+  }
+  const auto cost = [](const Key& k) { return (int64_t)std::get<1>(k) * std::get<2>(k); };
+  std::stable_sort(order.begin(), order.end(), [&](const Key& x, const Key& y) { return cost(x) > cost(y); });
+  for (const Key& k : order) {
+    std::vector<int32_t>& fs = sets[k];
+    std::stable_sort(fs.begin(), fs.end(),
+                     [&](int32_t x, int32_t y) { return P[x].min_node_size < P[y].min_node_size; });
+    const int32_t nt = std::get<5>(k);
+    for (size_t c = 0; c < fs.size(); c += kGroupMax) {
+      const size_t e = std::min(fs.size(), c + (size_t)kGroupMax);
+      for (int32_t t = 0; t < nt; ++t) {
+        first.push_back((int32_t)member.size());
+        for (size_t j = c; j < e; ++j) member.push_back((int32_t)(first_task[(size_t)fs[j]] + t));
+      }
+    }
+  }
+  first.push_back((int32_t)member.size());
+}
+
 // The fit of n_forests forests whose training (and held-out) rows are given
 // by L; validation of the arguments is done by the caller.
 void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_binner* binner, const double* y_log10,
@@ -378,6 +418,12 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   }
   F->pool_nodes = pool;
   const int64_t n_tasks = (int64_t)F->tasks.size();
+  const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
+  // a fused fit of several forests grows its trees in task groups
+  std::vector<int32_t> group_task, group_first;
+  if (n_forests > 1 && !plain) make_task_groups(params_host, n_forests, L, F->first_task, group_task, group_first);
+  const bool grouped = !group_first.empty();
+  const int64_t n_groups = grouped ? (int64_t)group_first.size() - 1 : n_tasks;
 
   F->d_tasks.reset((size_t)n_tasks, s);
   F->nodes.reset((size_t)pool, s);
@@ -394,9 +440,13 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   {
     std::vector<int64_t> bases((size_t)n_tasks);
     for (int64_t i = 0; i < n_tasks; ++i) bases[i] = F->tasks[i].node_base;
-    const HostPart parts[2] = {{F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * (size_t)n_tasks},
-                               {F->node_base.p, bases.data(), sizeof(int64_t) * (size_t)n_tasks}};
-    upload_staged(s, parts, 2);
+    F->group_task.reset(group_task.size(), s);
+    F->group_first.reset(group_first.size(), s);
+    const HostPart parts[4] = {{F->d_tasks.p, F->tasks.data(), sizeof(TreeTask) * (size_t)n_tasks},
+                               {F->node_base.p, bases.data(), sizeof(int64_t) * (size_t)n_tasks},
+                               {F->group_task.p, group_task.data(), sizeof(int32_t) * group_task.size()},
+                               {F->group_first.p, group_first.data(), sizeof(int32_t) * group_first.size()}};
+    upload_staged(s, parts, grouped ? 4 : 2);
   }
   F->train_rows.reset(train_rows.size(), s);
   DevBuf<int32_t>& d_train = F->train_rows;
@@ -412,13 +462,12 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   DevBuf<uint32_t> queue(1, s);
 
   GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
-  const bool plain = n_forests > 1 && (flags & AIWC_RF_FIT_PLAIN);
   bool tuned = false;
   if (flags & AIWC_RF_FIT_TUNE) {
     cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p, d_train.p, queue.p, s);
     tuned = true;
   }
-  const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max, grow_has_wide_phase(cfg));
+  const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max, grow_has_wide_phase(cfg), grouped);
   aiwc_rf_launch_info& LI = F->launch;
   LI.block = cfg.block;
   LI.waves_per_simd = grow_has_wide_phase(cfg) ? 4 : cfg.occupancy;
@@ -426,6 +475,7 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   LI.big_cols = effective_big_cols(cfg, mtry_max, n_cols);
   LI.wide_phase = grow_has_wide_phase(cfg) ? 1 : 0;
   LI.tuned = tuned ? 1 : 0;
+  LI.task_groups = (int32_t)n_groups;
 
   if (plain) {
     // one launch sequence per forest, as separate fits would issue them
@@ -448,11 +498,15 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
     AIWC_HIP(hipEventRecord(F->grow_end, s));
     LI.grid = grid_used;
   } else {
-    const int grid = grow_grid_size(cfg, n_tasks, mtry_max, n_cols);
+    const int grid = grow_grid_size(cfg, n_groups, mtry_max, n_cols, grouped);
     LI.grid = grid;
     DevBuf<uint8_t> scratch(per_wg * (size_t)grid, s);
-    const GrowLaunch g{codes, codes_p.p, d_train.p, F->d_tasks.p, (int32_t)n_tasks, F->nodes.p, F->node_N.p,
-                       F->n_nodes.p, F->work.p, F->inbag.p, queue.p, scratch.p, n_cap};
+    const GrowLaunch g{codes,     codes_p.p, d_train.p,
+                       F->d_tasks.p, (int32_t)n_tasks, F->nodes.p,
+                       F->node_N.p, F->n_nodes.p, F->work.p,
+                       F->inbag.p, queue.p,   scratch.p,
+                       n_cap,     grouped ? F->group_task.p : nullptr, grouped ? F->group_first.p : nullptr,
+                       (int32_t)n_groups};
     if (n_forests > 1) {
       // fused grid: the whole fit as one executable-graph launch (timing events
       // bracket the whole graph: reset, prepare, grow)

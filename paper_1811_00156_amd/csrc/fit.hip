@@ -115,9 +115,14 @@ struct Scratch {
   // p * cand_stride(mtry) + i (written by the wide batches, read by the partition
   // instead of the row's code line); null when the launch has no wide phase
   uint8_t* side;
+  // the entries and node sums of the level at which the trees of a group of
+  // tasks part (kept while each member grows on from it); unused (null) when
+  // the launch has no groups
+  Level2 SN;
 };
 
-__host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max, bool wide) {
+__host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max, bool wide,
+                                        bool grouped) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> uintptr_t {
     const size_t o = off;
@@ -158,6 +163,15 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   s->btask = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n_large * (size_t)mtry_max));
   s->side = wide ? reinterpret_cast<uint8_t*>(take(n * (size_t)cand_stride(mtry_max))) : nullptr;
+  s->SN = Level2{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (grouped) {
+    s->SN.buf = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.mstart = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.mend = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.mN = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.mS = reinterpret_cast<int64_t*>(take(8 * n));
+    s->SN.mQ = reinterpret_cast<uint64_t*>(take(8 * n));
+  }
   return off;
 }
 
@@ -183,6 +197,12 @@ struct GrowArgs {
   const int32_t* train_rows;
   const TreeTask* tasks;
   int32_t n_tasks;
+  // groups of tasks that differ only in min.node.size: group g's members are
+  // tasks group_task[group_first[g] .. group_first[g + 1]), by min.node.size
+  // ascending; null: every task is a group of its own, in task order
+  const int32_t* group_task;
+  const int32_t* group_first;
+  int32_t n_groups;
   uint64_t* nodes;
   uint32_t* node_N;
   int32_t* n_nodes;
@@ -753,6 +773,17 @@ struct Shared {
   uint32_t wstart[2][kWideMax], wlen[2][kWideMax], wcpre[2][kWideMax], wN[2][kWideMax];
   int64_t wS[2][kWideMax];
   alignas(8) uint8_t cand[2][256];
+  // the group being grown: its members' task indices, min.node.size, node
+  // slots and in-bag bitmaps, and the level at which their trees part (first
+  // node id, node count, next free id, entry buffer, levels grown)
+  int32_t gk, vi;  // members; the member being grown, -1 while their trees agree
+  int64_t vmin, vbase;  // its min.node.size and node slot
+  int32_t gtask[kGroupMax];
+  int32_t gmin[kGroupMax];
+  int64_t gbase[kGroupMax];
+  int64_t ginbag[kGroupMax];
+  uint32_t n_inbag;
+  uint32_t f_lo, f_cnt, f_next, f_cur, f_levels;
 };
 
 // Metadata of wide batch `bi` (nodes list[0 .. nb)) into buffer bi & 1.
@@ -1002,12 +1033,24 @@ __device__ __forceinline__ void bootstrap_counts(const TreeTask& T, int64_t n, u
   }
 }
 
+// The trees of one group: K tasks that differ only in min.node.size (sh.gtask,
+// by min.node.size ascending; a lone task is a group of one), T being the
+// first.  Their trees agree node for node down to the first level holding an
+// open node whose leaf rule depends on min.node.size (more weight than the
+// smallest value, at most the largest, and not pure), since every other step
+// (bootstrap, candidate draws by node id, searches, child ids) is the same.
+// The levels above it are grown once, with the smallest value; that level's
+// entries and node sums are then put aside, and each member in turn grows its
+// own tree on from them, after the shared levels' node words are copied into
+// its slot.  The work counters count the work done: a group's shared levels
+// count for its first member.
 // WIDE: the launch may hold nodes above the wide limit (the kernel without
 // the wide-batch phase is compiled separately, so that small training sets
-// keep its leaner register allocation).
-template <int BLOCK, bool WIDE>
-__device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, int32_t task_index, const Scratch& sc, uint8_t* lds,
-                          Shared& sh) {
+// keep its leaner register allocation).  GROUPED: the launch has groups (the
+// kernels of launches without compile the group logic out, which keeps their
+// register allocation as it was).
+template <int BLOCK, bool WIDE, bool GROUPED>
+__device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T, const Scratch& sc, uint8_t* lds, Shared& sh) {
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x, wid = tid / kWave, lane = (int)lane_id();
   const int64_t n = T.n_train;
@@ -1040,7 +1083,12 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
       // in-bag bitmap: this wave's 64 consecutive rows form one word
       const uint64_t bits = __ballot(c[r] > 0);
       const int64_t wbase = base + (int64_t)r * BLOCK + (int64_t)(tid / kWave) * kWave;
-      if (lane_id() == 0 && T.inbag_off >= 0 && wbase < n) a.inbag[T.inbag_off + wbase / kWave] = bits;
+      if (lane_id() == 0 && T.inbag_off >= 0 && wbase < n) {
+        if (GROUPED)
+          for (int v = 0; v < sh.gk; ++v) a.inbag[sh.ginbag[v] + wbase / kWave] = bits;
+        else
+          a.inbag[T.inbag_off + wbase / kWave] = bits;
+      }
     }
     uint32_t total;
     uint32_t pos = block_exscan<BLOCK>(mine, sh.tmp, total) + n_inbag;
@@ -1069,16 +1117,39 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     sc.L0.mQ[0] = Q0;
   }
   if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
-  if (tid == 0) sh.next_task = NW;
+  if (tid == 0) {
+    sh.next_task = NW;
+    sh.n_inbag = n_inbag;
+    sh.vi = sh.gk > 1 ? -1 : 0;
+    sh.vmin = sh.gmin[0];
+    sh.vbase = sh.gbase[0];
+  }
   __syncthreads();
 
   // threads that draw candidates each own a C-byte row of the LDS union area
   const int n_draw = min(BLOCK, (int)(a.union_bytes / (uint32_t)a.C));
-  const int64_t base_node = T.node_base;
+  // (the member being grown, its min.node.size and node slot are kept in the
+  // LDS, which spares registers across the level loop)
   uint32_t level_lo = 0, level_cnt = 1, next_id = 1;
   int cur = 0;
   uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0, work_hist = 0;
+  for (;;) {
+  bool parted = false;
   while (level_cnt > 0) {
+    if (GROUPED && sh.vi < 0) {
+      // does this level hold a node that is a leaf for some members only?
+      const Level2 C = cur ? sc.L1 : sc.L0;
+      const int64_t min_node = sh.vmin, m_hi = sh.gmin[sh.gk - 1];
+      bool dep = false;
+      for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+        const uint32_t N = C.mN[k];
+        if ((int64_t)N > min_node && (int64_t)N <= m_hi && !node_is_pure(N, C.mS[k], C.mQ[k])) dep = true;
+      }
+      if (__syncthreads_or(dep)) {
+        parted = true;
+        break;
+      }
+    }
     ++levels;
     const Level2 C = cur ? sc.L1 : sc.L0;  // this level
     const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
@@ -1086,13 +1157,14 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     // (a) leaf rules, candidate draws, tiers (the tier counts and the task
     // queue head were reset before the level began)
     if (tid < n_draw) {
+      const int64_t min_node = GROUPED ? sh.vmin : (int64_t)T.min_node;
       for (uint32_t k = tid; k < level_cnt; k += n_draw) {
         const uint32_t N = x.mN[k];
         const int64_t S = x.mS[k];
         const uint64_t Q = x.mQ[k];
         const uint32_t st = x.mstart[k];
         const uint32_t len = x.mend[k] - st;
-        if ((int64_t)N <= T.min_node || node_is_pure(N, S, Q)) {
+        if ((int64_t)N <= min_node || node_is_pure(N, S, Q)) {
           sc.status[k] = kLeaf;
           continue;
         }
@@ -1178,6 +1250,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     // live in the LDS union area (free until the next level) when the level's
     // nodes fit it, else in scratch.
     const bool lds_cur = level_cnt <= a.union_bytes / (uint32_t)sizeof(Cursor);
+    const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
     Cursor* lcur = reinterpret_cast<Cursor*>(lds);
     uint32_t n_split = 0, n_chunks = 0;
     for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
@@ -1290,18 +1363,96 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
     next_id += 2 * n_split;
     cur ^= 1;
   }
+  if (parted) {
+    // put the level aside (its open nodes' entries lie in [0, n_inbag)); the
+    // first member grows on from the level as it is
+    const Level2 C = cur ? sc.L1 : sc.L0;
+    const uint32_t ni = sh.n_inbag;
+    for (uint32_t i = tid; i < ni; i += BLOCK) sc.SN.buf[i] = C.buf[i];
+    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+      sc.SN.mstart[k] = C.mstart[k];
+      sc.SN.mend[k] = C.mend[k];
+      sc.SN.mN[k] = C.mN[k];
+      sc.SN.mS[k] = C.mS[k];
+      sc.SN.mQ[k] = C.mQ[k];
+    }
+    if (tid == 0) {
+      sh.f_lo = level_lo;
+      sh.f_cnt = level_cnt;
+      sh.f_next = next_id;
+      sh.f_cur = (uint32_t)cur;
+      sh.f_levels = (uint32_t)levels;
+    }
+    if (tid == 0) sh.vi = 0;
+    __syncthreads();
+    continue;
+  }
+  // the tree of member max(vi, 0) is complete
   work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
   work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, sh.red);
   work_part = block_sum<BLOCK, uint64_t>(work_part, sh.red);
   work_hist = block_sum<BLOCK, uint64_t>(work_hist, sh.red);
+  const int vi = GROUPED ? sh.vi : 0, K = GROUPED ? sh.gk : 1;
+  const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
+  const int v0 = vi < 0 ? 0 : vi;
+  // without a parting level every member's tree is the first one's
+  const int v1 = vi < 0 ? K : vi + 1;
+  for (int v = v0; v < v1; ++v) {
+    if (v > v0) {
+      const int64_t b = sh.gbase[v];
+      for (uint32_t i = tid; i < next_id; i += BLOCK) {
+        a.nodes[b + i] = a.nodes[base_node + i];
+        a.node_N[b + i] = a.node_N[base_node + i];
+      }
+    }
+    if (tid == 0) {
+      const int64_t ti = GROUPED ? sh.gtask[v] : sh.gtask[0];
+      a.n_nodes[ti] = (int32_t)next_id;
+      int64_t* wk = a.work + kWorkWords * ti;
+      const bool first = v == v0;
+      wk[0] = first ? (int64_t)work_rows : 0;
+      wk[1] = first ? (int64_t)work_nodes : 0;
+      wk[2] = first ? (int64_t)work_part : 0;
+      wk[3] = (int64_t)levels;
+      wk[4] = first ? (int64_t)work_hist : 0;
+    }
+  }
+  if (vi < 0 || vi + 1 == K) break;
+  // member vi + 1 grows on from the level put aside, with the shared levels'
+  // node words in its slot
+  const int64_t nbase = sh.gbase[vi + 1];
+  level_lo = sh.f_lo;
+  level_cnt = sh.f_cnt;
+  next_id = sh.f_next;
+  cur = (int)sh.f_cur;
+  levels = sh.f_levels;
+  work_rows = work_nodes = work_part = work_hist = 0;
+  {
+    const int64_t b0 = sh.gbase[0];
+    for (uint32_t i = tid; i < level_lo; i += BLOCK) {
+      a.nodes[nbase + i] = a.nodes[b0 + i];
+      a.node_N[nbase + i] = a.node_N[b0 + i];
+    }
+    const Level2 C = cur ? sc.L1 : sc.L0;
+    const uint32_t ni = sh.n_inbag;
+    for (uint32_t i = tid; i < ni; i += BLOCK) C.buf[i] = sc.SN.buf[i];
+    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+      C.mstart[k] = sc.SN.mstart[k];
+      C.mend[k] = sc.SN.mend[k];
+      C.mN[k] = sc.SN.mN[k];
+      C.mS[k] = sc.SN.mS[k];
+      C.mQ[k] = sc.SN.mQ[k];
+    }
+  }
+  __syncthreads();  // (every thread has read the member index)
+  if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
   if (tid == 0) {
-    a.n_nodes[task_index] = (int32_t)next_id;
-    int64_t* wk = a.work + kWorkWords * (int64_t)task_index;
-    wk[0] = (int64_t)work_rows;
-    wk[1] = (int64_t)work_nodes;
-    wk[2] = (int64_t)work_part;
-    wk[3] = (int64_t)levels;
-    wk[4] = (int64_t)work_hist;
+    sh.next_task = NW;
+    sh.vi = vi + 1;
+    sh.vmin = sh.gmin[vi + 1];
+    sh.vbase = nbase;
+  }
+  __syncthreads();
   }
   (void)wid;
 }
@@ -1309,7 +1460,7 @@ __device__ __forceinline__ void grow_tree(const GrowArgs& a, const TreeTask& T, 
 // OCC waves per SIMD (at most 512 / OCC VGPRs): the persistent kernel is bound
 // by latency, so resident waves can matter more than the registers it spills;
 // the kernel with the wide phase keeps four, the other is built for 4, 5 and 6.
-template <int BLOCK, bool WIDE, int OCC>
+template <int BLOCK, bool WIDE, int OCC, bool GROUPED>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) void k_grow(GrowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ Shared sh;
@@ -1318,19 +1469,67 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) vo
   // and let the fit report EINVAL
   if (__atomic_load_n(a.status, __ATOMIC_RELAXED) & kStatusBadCode) return;
   Scratch sc;
-  carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max, WIDE);
+  carve(&sc, reinterpret_cast<uintptr_t>(a.scratch) + a.scratch_stride * blockIdx.x, a.n_cap, a.mtry_max, WIDE,
+        GROUPED);
   for (int c = threadIdx.x; c < a.C; c += BLOCK) sh.nbins[c] = (uint16_t)a.n_bins[c];
   for (;;) {
     if (threadIdx.x == 0) sh.task = atomicAdd(a.queue, 1u);
     __syncthreads();
-    const uint32_t t = sh.task;
+    const uint32_t g = sh.task;
+    if (g >= (uint32_t)a.n_groups) return;
+    // the group's members (the host keeps a group within kGroupMax tasks)
+    const int32_t gf = GROUPED ? a.group_first[g] : (int32_t)g;
+    const int K = GROUPED ? min(a.group_first[g + 1] - gf, kGroupMax) : 1;
+    if (threadIdx.x == 0) sh.gk = K;
+    if (threadIdx.x < K) {
+      const int32_t ti = GROUPED ? a.group_task[gf + threadIdx.x] : (int32_t)g;
+      sh.gtask[threadIdx.x] = ti;
+      sh.gmin[threadIdx.x] = a.tasks[ti].min_node;
+      sh.gbase[threadIdx.x] = a.tasks[ti].node_base;
+      sh.ginbag[threadIdx.x] = a.tasks[ti].inbag_off;
+    }
     __syncthreads();
-    if (t >= (uint32_t)a.n_tasks) return;
-    const TreeTask T = a.tasks[t];
-    grow_tree<BLOCK, WIDE>(a, T, (int32_t)t, sc, lds, sh);
+    const TreeTask T = a.tasks[rfl((uint32_t)sh.gtask[0])];
+    grow_group<BLOCK, WIDE, GROUPED>(a, T, sc, lds, sh);
     __syncthreads();
   }
 }
+
+// The grow kernel of this translation unit for a launch shape (block, wide
+// phase, waves per SIMD): the kernels for launches with task groups are built
+// in a unit of their own (which includes this file with AIWC_GROW_GROUPED set),
+// so that the two sets compile in parallel.
+#ifndef AIWC_GROW_GROUPED
+#define AIWC_GROW_GROUPED 0
+#endif
+template <int BLOCK>
+const void* grow_kernel(bool wide, int occ) {
+  constexpr bool G = AIWC_GROW_GROUPED != 0;
+  if (wide) return reinterpret_cast<const void*>(k_grow<BLOCK, true, 4, G>);
+  switch (occ) {
+    case 5: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 5, G>);
+    case 6: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 6, G>);
+    default: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 4, G>);
+  }
+}
+
+const void* grow_kernel_block(int block, bool wide, int occ) {
+  switch (block) {
+    case 192: return grow_kernel<192>(wide, occ);
+    case 256: return grow_kernel<256>(wide, occ);
+    case 512: return grow_kernel<512>(wide, occ);
+    case 1024: return grow_kernel<1024>(wide, occ);
+    default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
+  }
+}
+
+#if AIWC_GROW_GROUPED
+}  // namespace
+
+const void* grow_kernel_grouped(int block, bool wide, int occ) { return grow_kernel_block(block, wide, occ); }
+
+}  // namespace aiwc
+#else
 
 __global__ void k_init(uint32_t* status, uint32_t* queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -1404,25 +1603,9 @@ Layout grow_layout(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
   return L;
 }
 
-// The grow kernel for a launch shape (block, wide phase, waves per SIMD).
-template <int BLOCK>
-const void* grow_kernel(bool wide, int occ) {
-  if (wide) return reinterpret_cast<const void*>(k_grow<BLOCK, true, 4>);
-  switch (occ) {
-    case 5: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 5>);
-    case 6: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 6>);
-    default: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 4>);
-  }
-}
-
-const void* grow_kernel_for(const GrowConfig& cfg, bool wide) {
-  switch (cfg.block) {
-    case 192: return grow_kernel<192>(wide, cfg.occupancy);
-    case 256: return grow_kernel<256>(wide, cfg.occupancy);
-    case 512: return grow_kernel<512>(wide, cfg.occupancy);
-    case 1024: return grow_kernel<1024>(wide, cfg.occupancy);
-    default: fail(AIWC_RF_EINVAL, "unsupported grow block size");
-  }
+const void* grow_kernel_for(const GrowConfig& cfg, bool wide, bool grouped) {
+  return grouped ? grow_kernel_grouped(cfg.block, wide, cfg.occupancy)
+                 : grow_kernel_block(cfg.block, wide, cfg.occupancy);
 }
 
 int occupancy(const void* kernel, int block, uint32_t lds) {
@@ -1444,9 +1627,9 @@ void launch_set_i32(int32_t* p, int32_t v, hipStream_t s) {
   AIWC_HIP(hipGetLastError());
 }
 
-size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide) {
+size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide, bool grouped) {
   Scratch s;
-  return carve(&s, 0, n_cap, mtry_max, wide);
+  return carve(&s, 0, n_cap, mtry_max, wide, grouped);
 }
 
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
@@ -1457,10 +1640,10 @@ void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d
   AIWC_HIP(hipGetLastError());
 }
 
-int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C) {
+int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C, bool grouped) {
   const uint32_t lds = grow_layout(cfg, mtry_max, C).union_bytes;
   if (lds > device_info().lds_per_block) fail(AIWC_RF_EINVAL, "grow kernel LDS exceeds the device limit");
-  int per_cu = occupancy(grow_kernel_for(cfg, grow_has_wide_phase(cfg)), cfg.block, lds);
+  int per_cu = occupancy(grow_kernel_for(cfg, grow_has_wide_phase(cfg), grouped), cfg.block, lds);
   if (per_cu < 1) fail(AIWC_RF_ENOMEM, "grow kernel does not fit the device (LDS or registers)");
   if (cfg.wg_per_cu > 0) per_cu = std::min(per_cu, cfg.wg_per_cu);
   const int64_t slots = (int64_t)device_info().cus * per_cu;
@@ -1484,6 +1667,9 @@ GrowArgs grow_args(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const 
   a.train_rows = g.train_rows;
   a.tasks = g.tasks;
   a.n_tasks = g.n_tasks;
+  a.group_task = g.group_task;
+  a.group_first = g.group_first;
+  a.n_groups = g.group_first ? g.n_groups : g.n_tasks;
   a.nodes = g.nodes;
   a.node_N = g.node_N;
   a.n_nodes = g.n_nodes;
@@ -1496,7 +1682,7 @@ GrowArgs grow_args(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const 
   a.mtry_max = mtry_max;
   a.huge_min = cfg.huge_min;
   a.wide_sums = cfg.wide_sums ? 1 : 0;
-  a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max, grow_has_wide_phase(cfg));
+  a.scratch_stride = grow_scratch_bytes(g.n_cap, mtry_max, grow_has_wide_phase(cfg), g.group_first != nullptr);
   const Layout L = grow_layout(cfg, mtry_max, C);
   a.union_bytes = L.union_bytes;
   a.wave_bytes = L.wave_bytes;
@@ -1565,7 +1751,7 @@ int effective_big_cols(const GrowConfig& cfg, int32_t mtry_max, int32_t C) {
 void launch_grow(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const int32_t* d_n_bins, const int64_t* y_fp,
                  uint32_t* d_status, int32_t mtry_max, int grid, hipStream_t s) {
   GrowArgs a = grow_args(cfg, g, C, d_n_bins, y_fp, d_status, mtry_max);
-  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg));
+  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg), g.group_first != nullptr);
   void* args[] = {&a};
   AIWC_HIP(hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, a.union_bytes, s));
   AIWC_HIP(hipGetLastError());
@@ -1575,7 +1761,7 @@ bool launch_fit_graph(const GrowConfig& cfg, const GrowLaunch& g, const uint8_t*
                       const int32_t* d_n_bins, const double* y, int64_t* y_fp, uint32_t* d_status, int32_t mtry_max,
                       int grid, hipStream_t s) {
   GrowArgs a = grow_args(cfg, g, C, d_n_bins, y_fp, d_status, mtry_max);
-  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg));
+  const void* kernel = grow_kernel_for(cfg, grow_has_wide_phase(cfg), g.group_first != nullptr);
   const int pb = prepare_blocks(n, C);
   int32_t Cp = padded_cols(C);
   uint32_t* queue = g.queue;
@@ -1635,3 +1821,4 @@ bool launch_fit_graph(const GrowConfig& cfg, const GrowLaunch& g, const uint8_t*
 }
 
 }  // namespace aiwc
+#endif

@@ -156,6 +156,10 @@ struct TreeTask {
 // candidate column of every node above 32 rows).
 constexpr int kWorkWords = 5;
 
+// Most tasks in a group of a fused fit: trees that differ only in
+// min.node.size, grown together up to the level where they part.
+constexpr int kGroupMax = 8;
+
 // Status bits a fit raises on the device.
 constexpr uint32_t kStatusBadY = 1u;
 constexpr uint32_t kStatusBadCode = 2u;
@@ -177,6 +181,8 @@ struct aiwc_rf_forest {
   aiwc::DevBuf<int32_t> n_nodes;           // per task
   aiwc::DevBuf<int64_t> work;              // per task: kWorkWords counters
   aiwc::DevBuf<int64_t> node_base;         // per task, device copy for traversal
+  aiwc::DevBuf<int32_t> group_task;        // task groups of a fused fit (members, by group)
+  aiwc::DevBuf<int32_t> group_first;       // first member of every group, and the member count
   aiwc::DevBuf<uint32_t> status;           // device status word
   uint32_t* status_host = nullptr;         // pinned
   hipEvent_t done = nullptr;
@@ -259,9 +265,14 @@ inline int32_t padded_cols(int32_t C) {
 void launch_prepare(const uint8_t* codes, int64_t n, int32_t C, const int32_t* d_n_bins, const double* y,
                     int64_t* y_fp, uint8_t* codes_p, uint32_t* d_status, hipStream_t s);
 // Scratch of one grow workgroup (wide: the launch has the wide phase, whose
-// rows also keep their candidate codes for the partition).
-size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide);
-int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C);
+// rows also keep their candidate codes for the partition; grouped: it grows
+// groups of tasks, which put aside the level where their trees part).
+size_t grow_scratch_bytes(int64_t n_cap, int32_t mtry_max, bool wide, bool grouped);
+// Workgroups of a persistent grow launch over n_tasks work items (grouped: the
+// kernel for launches with task groups).
+int grow_grid_size(const GrowConfig& cfg, int64_t n_tasks, int32_t mtry_max, int32_t C, bool grouped = false);
+// The grow kernels for launches with task groups (fit_grouped.hip).
+const void* grow_kernel_grouped(int block, bool wide, int occ);
 // The buffers of one grow launch: the codes (dense and row-padded), the
 // training-row lists, the tasks and everything the trees write.
 struct GrowLaunch {
@@ -278,6 +289,10 @@ struct GrowLaunch {
   uint32_t* queue;
   uint8_t* scratch;
   int64_t n_cap;
+  // groups of tasks grown together (null: each task alone)
+  const int32_t* group_task = nullptr;
+  const int32_t* group_first = nullptr;
+  int32_t n_groups = 0;
 };
 void launch_grow(const GrowConfig& cfg, const GrowLaunch& g, int32_t C, const int32_t* d_n_bins, const int64_t* y_fp,
                  uint32_t* d_status, int32_t mtry_max, int grid, hipStream_t s);

@@ -93,7 +93,8 @@ class LaunchInfo(ctypes.Structure):
 
     _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("wide_limit", ctypes.c_int32),
                 ("big_cols", ctypes.c_int32), ("grid", ctypes.c_int32), ("wide_phase", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("graph_reused", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("graph_reused", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("task_groups", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

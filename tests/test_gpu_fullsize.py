@@ -69,7 +69,7 @@ def test_c3_every_tree_and_predictions(rf, c3, tuned):
                             rf.make_params(C3["num_trees"], C3["mtry"], C3["min_node"], True, 1), flags=flags)
     li = forest.launch()
     log(f"c3 launch shape {li}")
-    assert li["wide_phase"] == 1
+    assert li["wide_phase"] == 1 and li["task_groups"] == C3["num_trees"]
     if not tuned:
         assert li["block"] == 1024 and li["wide_limit"] == 512
     compare_forest(forest, of, C3["num_trees"], f"C3 ({'tuned' if tuned else 'default'} shape)")
@@ -110,6 +110,8 @@ def test_grid_default_shape(grid):
     # 435200 trees on 2000-row training sets: the shape every trees-per-CU-full
     # grid takes (and the one the fused benchmark times unless it is tuned)
     assert (li["block"], li["waves_per_simd"], li["big_cols"], li["wide_phase"], li["graph"]) == (192, 6, 4, 0, 1)
+    # tree t of the five forests of each (fold, mtry) is one task group
+    assert li["task_groups"] == 10 * 34 * 256
 
 
 def test_grid_seeded_subset(rf, oracle, grid):
