@@ -115,10 +115,21 @@ struct Scratch {
   // p * cand_stride(mtry) + i (written by the wide batches, read by the partition
   // instead of the row's code line); null when the launch has no wide phase
   uint8_t* side;
-  // the entries and node sums of the level at which the trees of a group of
-  // tasks part (kept while each member grows on from it); unused (null) when
-  // the launch has no groups
-  Level2 SN;
+  // the level at which the trees of a group of tasks part, as its split
+  // searches left it (kept while each member grows on from it): this level's
+  // entries and node sums, the next level's entries (the small nodes' rows,
+  // placed by their searches), and the per-node search results and records;
+  // null when the launch has no groups
+  struct Parted {
+    Level2 L;
+    uint64_t* nbuf;
+    uint8_t *status, *dcol, *dbin;
+    uint32_t *ridx, *dNL, *dcnt;
+    int64_t* dSL;
+    uint64_t* dQL;
+    Rec* recs;
+    uint8_t* side;
+  } SN;
 };
 
 __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_cap, int32_t mtry_max, bool wide,
@@ -163,14 +174,25 @@ __host__ __device__ inline size_t carve(Scratch* s, uintptr_t base, int64_t n_ca
   s->recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
   s->btask = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * n_large * (size_t)mtry_max));
   s->side = wide ? reinterpret_cast<uint8_t*>(take(n * (size_t)cand_stride(mtry_max))) : nullptr;
-  s->SN = Level2{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  s->SN = Scratch::Parted{};
   if (grouped) {
-    s->SN.buf = reinterpret_cast<uint64_t*>(take(8 * n));
-    s->SN.mstart = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->SN.mend = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->SN.mN = reinterpret_cast<uint32_t*>(take(4 * n));
-    s->SN.mS = reinterpret_cast<int64_t*>(take(8 * n));
-    s->SN.mQ = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.L.buf = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.L.mstart = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.L.mend = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.L.mN = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.L.mS = reinterpret_cast<int64_t*>(take(8 * n));
+    s->SN.L.mQ = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.nbuf = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.status = reinterpret_cast<uint8_t*>(take(n));
+    s->SN.dcol = reinterpret_cast<uint8_t*>(take(n));
+    s->SN.dbin = reinterpret_cast<uint8_t*>(take(n));
+    s->SN.ridx = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.dNL = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.dcnt = reinterpret_cast<uint32_t*>(take(4 * n));
+    s->SN.dSL = reinterpret_cast<int64_t*>(take(8 * n));
+    s->SN.dQL = reinterpret_cast<uint64_t*>(take(8 * n));
+    s->SN.recs = reinterpret_cast<Rec*>(take(sizeof(Rec) * n_large * (size_t)mtry_max));
+    s->SN.side = wide ? reinterpret_cast<uint8_t*>(take(n * (size_t)cand_stride(mtry_max))) : nullptr;
   }
   return off;
 }
@@ -775,7 +797,8 @@ struct Shared {
   alignas(8) uint8_t cand[2][256];
   // the group being grown: its members' task indices, min.node.size, node
   // slots and in-bag bitmaps, and the level at which their trees part (first
-  // node id, node count, next free id, entry buffer, levels grown)
+  // node id, node count, next free id, entry buffer, levels grown, large and
+  // wide nodes)
   int32_t gk, vi;  // members; the member being grown, -1 while their trees agree
   int64_t vmin, vbase;  // its min.node.size and node slot
   int32_t gtask[kGroupMax];
@@ -783,7 +806,9 @@ struct Shared {
   int64_t gbase[kGroupMax];
   int64_t ginbag[kGroupMax];
   uint32_t n_inbag;
-  uint32_t f_lo, f_cnt, f_next, f_cur, f_levels;
+  uint32_t f_lo, f_cnt, f_next, f_cur, f_levels, f_big, f_huge;
+  uint32_t part;    // this level holds a node that is a leaf for some members only
+  uint32_t resume;  // the member grows on from the decisions of the parting level
 };
 
 // Metadata of wide batch `bi` (nodes list[0 .. nb)) into buffer bi & 1.
@@ -1039,11 +1064,14 @@ __device__ __forceinline__ void bootstrap_counts(const TreeTask& T, int64_t n, u
 // open node whose leaf rule depends on min.node.size (more weight than the
 // smallest value, at most the largest, and not pure), since every other step
 // (bootstrap, candidate draws by node id, searches, child ids) is the same.
-// The levels above it are grown once, with the smallest value; that level's
-// entries and node sums are then put aside, and each member in turn grows its
-// own tree on from them, after the shared levels' node words are copied into
-// its slot.  The work counters count the work done: a group's shared levels
-// count for its first member.
+// Those levels, and the split searches of the parting level itself, are done
+// once, with the smallest value (every node open for some member is searched,
+// and a search does not depend on min.node.size).  The parting level's state
+// is then put aside as the searches left it, and each member in turn grows its
+// own tree on from its decisions: the nodes of at most its min.node.size are
+// made leaves, the shared levels' node words are copied into its slot.  The
+// work counters count the work done: the shared levels, searches included,
+// count for the group's first member.
 // WIDE: the launch may hold nodes above the wide limit (the kernel without
 // the wide-batch phase is compiled separately, so that small training sets
 // keep its leaner register allocation).  GROUPED: the launch has groups (the
@@ -1123,6 +1151,8 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
     sh.vi = sh.gk > 1 ? -1 : 0;
     sh.vmin = sh.gmin[0];
     sh.vbase = sh.gbase[0];
+    sh.part = 0;
+    sh.resume = 0;
   }
   __syncthreads();
 
@@ -1134,30 +1164,20 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
   int cur = 0;
   uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0, work_hist = 0;
   for (;;) {
-  bool parted = false;
   while (level_cnt > 0) {
-    if (GROUPED && sh.vi < 0) {
-      // does this level hold a node that is a leaf for some members only?
-      const Level2 C = cur ? sc.L1 : sc.L0;
-      const int64_t min_node = sh.vmin, m_hi = sh.gmin[sh.gk - 1];
-      bool dep = false;
-      for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-        const uint32_t N = C.mN[k];
-        if ((int64_t)N > min_node && (int64_t)N <= m_hi && !node_is_pure(N, C.mS[k], C.mQ[k])) dep = true;
-      }
-      if (__syncthreads_or(dep)) {
-        parted = true;
-        break;
-      }
-    }
-    ++levels;
     const Level2 C = cur ? sc.L1 : sc.L0;  // this level
     const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
     const Ctx x{&a, &T, sc, C.buf, X.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
+    // (a) - (c) are skipped by a member that grows on from the parting level
+    if (!GROUPED || !sh.resume) {
+    ++levels;
     // (a) leaf rules, candidate draws, tiers (the tier counts and the task
     // queue head were reset before the level began)
     if (tid < n_draw) {
       const int64_t min_node = GROUPED ? sh.vmin : (int64_t)T.min_node;
+      // while the members' trees agree: an open node of at most the largest
+      // member's min.node.size is a leaf for some members only
+      const int64_t m_part = GROUPED && sh.vi < 0 ? (int64_t)sh.gmin[sh.gk - 1] : -1;
       for (uint32_t k = tid; k < level_cnt; k += n_draw) {
         const uint32_t N = x.mN[k];
         const int64_t S = x.mS[k];
@@ -1168,6 +1188,7 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
           sc.status[k] = kLeaf;
           continue;
         }
+        if (GROUPED && (int64_t)N <= m_part) sh.part = 1u;
         work_rows += len;
         ++work_nodes;
         // nodes above 32 rows add each row to an LDS bin per candidate column
@@ -1243,6 +1264,50 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
       }
     }
     __syncthreads();
+    if (GROUPED && sh.part) {
+      // the members' trees part at this level: put its searched state aside
+      // (the open nodes' entries lie in [0, n_inbag)); the first member goes on
+      const uint32_t ni = sh.n_inbag;
+      for (uint32_t i = tid; i < ni; i += BLOCK) {
+        sc.SN.L.buf[i] = C.buf[i];
+        sc.SN.nbuf[i] = X.buf[i];
+      }
+      for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+        sc.SN.L.mstart[k] = C.mstart[k];
+        sc.SN.L.mend[k] = C.mend[k];
+        sc.SN.L.mN[k] = C.mN[k];
+        sc.SN.L.mS[k] = C.mS[k];
+        sc.SN.L.mQ[k] = C.mQ[k];
+        sc.SN.status[k] = sc.status[k];
+        sc.SN.ridx[k] = sc.ridx[k];
+        sc.SN.dcol[k] = sc.dcol[k];
+        sc.SN.dbin[k] = sc.dbin[k];
+        sc.SN.dNL[k] = sc.dNL[k];
+        sc.SN.dSL[k] = sc.dSL[k];
+        sc.SN.dcnt[k] = sc.dcnt[k];
+        sc.SN.dQL[k] = sc.dQL[k];
+      }
+      for (uint32_t i = tid; i < (n_big + n_huge) * (uint32_t)mtry; i += BLOCK) sc.SN.recs[i] = sc.recs[i];
+      if (WIDE && n_huge > 0) {
+        const uint4* src = reinterpret_cast<const uint4*>(sc.side);
+        uint4* dst = reinterpret_cast<uint4*>(sc.SN.side);
+        for (uint32_t i = tid; i < ni * (uint32_t)cand_stride(mtry) / 16u; i += BLOCK) dst[i] = src[i];
+      }
+      __syncthreads();  // (every thread has read the flag)
+      if (tid == 0) {
+        sh.part = 0;
+        sh.vi = 0;
+        sh.f_lo = level_lo;
+        sh.f_cnt = level_cnt;
+        sh.f_next = next_id;
+        sh.f_cur = (uint32_t)cur;
+        sh.f_levels = (uint32_t)levels;
+        sh.f_big = n_big;
+        sh.f_huge = n_huge;
+      }
+    }
+    }
+    const uint32_t n_big = sh.cnt[1];
     // (d) the large and wide nodes' decisions from their records (the wide
     // nodes' records follow the large nodes'), then (e) breadth-first child
     // ids, node words, children's sums and cursors, and the partition's chunks
@@ -1356,36 +1421,15 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
     }
     // the next level's tier counts and task queue head
     if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
-    if (tid == 0) sh.next_task = NW;
+    if (tid == 0) {
+      sh.next_task = NW;
+      if (GROUPED) sh.resume = 0;
+    }
     __syncthreads();
     level_lo = next_id;
     level_cnt = 2 * n_split;
     next_id += 2 * n_split;
     cur ^= 1;
-  }
-  if (parted) {
-    // put the level aside (its open nodes' entries lie in [0, n_inbag)); the
-    // first member grows on from the level as it is
-    const Level2 C = cur ? sc.L1 : sc.L0;
-    const uint32_t ni = sh.n_inbag;
-    for (uint32_t i = tid; i < ni; i += BLOCK) sc.SN.buf[i] = C.buf[i];
-    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-      sc.SN.mstart[k] = C.mstart[k];
-      sc.SN.mend[k] = C.mend[k];
-      sc.SN.mN[k] = C.mN[k];
-      sc.SN.mS[k] = C.mS[k];
-      sc.SN.mQ[k] = C.mQ[k];
-    }
-    if (tid == 0) {
-      sh.f_lo = level_lo;
-      sh.f_cnt = level_cnt;
-      sh.f_next = next_id;
-      sh.f_cur = (uint32_t)cur;
-      sh.f_levels = (uint32_t)levels;
-    }
-    if (tid == 0) sh.vi = 0;
-    __syncthreads();
-    continue;
   }
   // the tree of member max(vi, 0) is complete
   work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
@@ -1418,9 +1462,10 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
     }
   }
   if (vi < 0 || vi + 1 == K) break;
-  // member vi + 1 grows on from the level put aside, with the shared levels'
-  // node words in its slot
-  const int64_t nbase = sh.gbase[vi + 1];
+  // member vi + 1 grows on from the parting level's decisions: its searched
+  // state restored, the nodes of at most its min.node.size made leaves, the
+  // shared levels' node words copied into its slot
+  const int64_t nbase = sh.gbase[vi + 1], m_v = sh.gmin[vi + 1];
   level_lo = sh.f_lo;
   level_cnt = sh.f_cnt;
   next_id = sh.f_next;
@@ -1428,29 +1473,51 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
   levels = sh.f_levels;
   work_rows = work_nodes = work_part = work_hist = 0;
   {
+    const uint32_t f_big = sh.f_big, f_huge = sh.f_huge;
     const int64_t b0 = sh.gbase[0];
     for (uint32_t i = tid; i < level_lo; i += BLOCK) {
       a.nodes[nbase + i] = a.nodes[b0 + i];
       a.node_N[nbase + i] = a.node_N[b0 + i];
     }
     const Level2 C = cur ? sc.L1 : sc.L0;
+    const Level2 X = cur ? sc.L0 : sc.L1;
     const uint32_t ni = sh.n_inbag;
-    for (uint32_t i = tid; i < ni; i += BLOCK) C.buf[i] = sc.SN.buf[i];
-    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-      C.mstart[k] = sc.SN.mstart[k];
-      C.mend[k] = sc.SN.mend[k];
-      C.mN[k] = sc.SN.mN[k];
-      C.mS[k] = sc.SN.mS[k];
-      C.mQ[k] = sc.SN.mQ[k];
+    for (uint32_t i = tid; i < ni; i += BLOCK) {
+      C.buf[i] = sc.SN.L.buf[i];
+      X.buf[i] = sc.SN.nbuf[i];
     }
+    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+      const uint32_t N = sc.SN.L.mN[k];
+      C.mstart[k] = sc.SN.L.mstart[k];
+      C.mend[k] = sc.SN.L.mend[k];
+      C.mN[k] = N;
+      C.mS[k] = sc.SN.L.mS[k];
+      C.mQ[k] = sc.SN.L.mQ[k];
+      const uint8_t st = sc.SN.status[k];
+      sc.status[k] = (int64_t)N <= m_v ? kLeaf : st;
+      sc.ridx[k] = sc.SN.ridx[k];
+      sc.dcol[k] = sc.SN.dcol[k];
+      sc.dbin[k] = sc.SN.dbin[k];
+      sc.dNL[k] = sc.SN.dNL[k];
+      sc.dSL[k] = sc.SN.dSL[k];
+      sc.dcnt[k] = sc.SN.dcnt[k];
+      sc.dQL[k] = sc.SN.dQL[k];
+    }
+    for (uint32_t i = tid; i < (f_big + f_huge) * (uint32_t)mtry; i += BLOCK) sc.recs[i] = sc.SN.recs[i];
+    if (WIDE && f_huge > 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(sc.SN.side);
+      uint4* dst = reinterpret_cast<uint4*>(sc.side);
+      for (uint32_t i = tid; i < ni * (uint32_t)cand_stride(mtry) / 16u; i += BLOCK) dst[i] = src[i];
+    }
+    __syncthreads();  // (every thread has read the member index)
+    if (tid < 3 + kSegClasses) sh.cnt[tid] = tid == 1 ? f_big : tid == 2 ? f_huge : 0u;
   }
-  __syncthreads();  // (every thread has read the member index)
-  if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
   if (tid == 0) {
     sh.next_task = NW;
     sh.vi = vi + 1;
-    sh.vmin = sh.gmin[vi + 1];
+    sh.vmin = m_v;
     sh.vbase = nbase;
+    sh.resume = 1;
   }
   __syncthreads();
   }
