@@ -13,6 +13,9 @@ grows each forest's tree on from it.  The cases:
 Every tree of every forest, node for node, and the out-of-bag sums and counts of
 every forest (each member's in-bag bitmap is written by its group).  The same
 forests fitted with one launch per forest (no groups) must equal them too.
+A larger training set (24000 rows, 256 bins) runs the groups in the kernel with
+the workgroup-wide phase, parting where some nodes are still wide (their rows'
+candidate codes are put aside and restored with the level).
 Tolerance zero: node arrays, leaf sums and integer out-of-bag sums.
 """
 import numpy as np
@@ -99,3 +102,31 @@ def test_groups_oob(rf, oracle, setup):
         assert np.array_equal(counts[off:off + n], cnt), f"forest {k} {FORESTS[k]}: out-of-bag counts"
         assert res.rows[k] == rows
         off += n
+
+
+# (trees, mtry, min.node.size): one group of four (min.node.size 700 parts the
+# trees while other nodes of the level still have more than 512 rows) and a
+# forest of another mtry, a group of its own
+WIDE_FORESTS = [(6, 16, mn) for mn in (5, 1, 700, 60)] + [(6, 8, 5)]
+WIDE_ROWS = 24000
+
+
+def test_groups_wide_kernel(rf, oracle):
+    d3 = synth.d3()
+    rows = np.sort(np.random.default_rng(181100162).choice(d3.n, size=WIDE_ROWS, replace=False))
+    X, dev_id, y = np.ascontiguousarray(d3.X[rows]), np.ascontiguousarray(d3.device[rows]), np.ascontiguousarray(d3.y[rows])
+    ob = oracle.bin(X, dev_id, d3.n_devices, 256)
+    params = [rf.make_params(nt, m, mn, True, 5) for nt, m, mn in WIDE_FORESTS]
+    binner = rf.aiwc_rf_binner_from_counts(ob.n_bins)
+    log(f"groups wide: fused fit of {len(WIDE_FORESTS)} forests on {WIDE_ROWS} rows")
+    forest = rf.aiwc_rf_fit(to_dev(ob.codes), binner, to_dev(y), params, heldout_fold=[-1] * len(WIDE_FORESTS),
+                            flags=rf.FIT_FUSED)
+    li = forest.launch()
+    log(f"groups wide: launch {li}")
+    assert li["wide_phase"] == 1 and li["block"] == 1024
+    assert li["task_groups"] == 6 + 6
+    for k, (nt, m, mn) in enumerate(WIDE_FORESTS):
+        of = oracle.fit(ob.codes, ob.n_bins, y, nt, m, mn, seed=5, n_threads=0)
+        trees = forest.export(k)
+        for t in range(nt):
+            assert_tree_equal(trees[t], of.tree(t), f"wide forest {k} {WIDE_FORESTS[k]} tree {t}")
