@@ -47,21 +47,34 @@ int32_t status_to_code(uint32_t st, std::string& msg) {
   return AIWC_RF_OK;
 }
 
-GrowConfig grow_config(int64_t n_cap, int64_t n_tasks, const std::vector<int32_t>& n_bins) {
+GrowConfig grow_config(int64_t n_cap, int64_t n_items, const std::vector<int32_t>& n_bins) {
   GrowConfig cfg;
-  // large training sets: 1024 threads per tree, nodes above 512 rows in
+  // n_items: the launch's work items (trees, or task groups of a fused fit).
+  // Large training sets: 1024 threads per tree, nodes above 512 rows in
   // workgroup-wide batches (the autotuner's choice on 200000 rows, 2 % ahead
-  // of 512 threads with every node above 64 rows in batches); small ones: 512
-  // threads per tree while trees are few, and once there are enough trees to
-  // fill several workgroups per CU, 192 threads at 6 waves per SIMD (eight
-  // resident trees per CU).  A large-node task takes two candidate columns
-  // while trees are few (more tasks per node for the tree's waves), up to four
-  // once the CUs are full.
+  // of 512 threads with every node above 64 rows in batches).  Small ones, by
+  // work items per CU: below 4, 512 threads per tree; from 4, 192 threads at 6
+  // waves per SIMD (eight resident trees per CU); from 16, 128 threads at 6
+  // waves (twelve); from 64, 64 threads at 5 waves (twenty): a tree's levels
+  // get fewer waves, which pays once the queue is deep enough that the CUs
+  // stay full to the end (the tuning grid, 340 groups per CU: 380 ms against
+  // 395 and 417; one fold of it, 34 per CU: 45 ms against 42 and 43).  A
+  // large-node task takes two candidate columns while trees are few (more
+  // tasks per node for the tree's waves), up to four once the CUs are full.
   cfg.big_cols = 2;
+  const int64_t cus = device_info().cus;
   if (n_cap > 16384) {
     cfg.block = 1024;
     cfg.huge_min = 512;
-  } else if (n_tasks >= 4LL * device_info().cus) {
+  } else if (n_items >= 64 * cus) {
+    cfg.block = 64;
+    cfg.occupancy = 5;
+    cfg.big_cols = 4;
+  } else if (n_items >= 16 * cus) {
+    cfg.block = 128;
+    cfg.occupancy = 6;
+    cfg.big_cols = 4;
+  } else if (n_items >= 4 * cus) {
     cfg.block = 192;
     cfg.occupancy = 6;
     cfg.big_cols = 4;
@@ -120,12 +133,12 @@ int ilog2_ceil(int64_t v) {
 // The autotuner: time every candidate launch shape on the call's first trees
 // (they are grown again by the real launch, with identical results) and keep
 // the fastest for this problem shape.
-GrowConfig tune_grow(const GrowConfig& base, int32_t n_cols, int32_t mtry_max, aiwc_rf_forest* F,
+GrowConfig tune_grow(const GrowConfig& base, int64_t n_items, int32_t n_cols, int32_t mtry_max, aiwc_rf_forest* F,
                      const uint8_t* codes, int64_t n, const aiwc_rf_binner* binner, const double* y, int64_t* y_fp,
                      uint8_t* codes_p,
                      const int32_t* d_train, uint32_t* queue, hipStream_t s) {
   const int64_t n_tasks = (int64_t)F->tasks.size();
-  TuneKey key{device_info().cus, ilog2_ceil(base.n_cap), n_cols, base.bins_max, mtry_max, ilog2_ceil(n_tasks)};
+  TuneKey key{device_info().cus, ilog2_ceil(base.n_cap), n_cols, base.bins_max, mtry_max, ilog2_ceil(n_items)};
   GrowConfig best = base;
   if (tune_lookup(key, &best)) return best;
   const int64_t trial = std::min<int64_t>(n_tasks, 64LL * device_info().cus);
@@ -461,10 +474,19 @@ void fit_common(const uint8_t* codes, int64_t n, int32_t n_cols, const aiwc_rf_b
   DevBuf<uint8_t> codes_p((size_t)n * padded_cols(n_cols) + 64, s);  // slack for 80-byte reads of the last row
   DevBuf<uint32_t> queue(1, s);
 
-  GrowConfig cfg = grow_config(n_cap, n_tasks, binner->n_bins);
+  // the work items of the (largest) launch: the task groups of a fused fit,
+  // a forest's trees when every forest is launched on its own, as separate
+  // fits would be
+  int64_t n_items = n_groups;
+  if (plain) {
+    n_items = 0;
+    for (int32_t f = 0; f < n_forests; ++f) n_items = std::max<int64_t>(n_items, params_host[f].num_trees);
+  }
+  GrowConfig cfg = grow_config(n_cap, n_items, binner->n_bins);
   bool tuned = false;
   if (flags & AIWC_RF_FIT_TUNE) {
-    cfg = tune_grow(cfg, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p, d_train.p, queue.p, s);
+    cfg = tune_grow(cfg, n_items, n_cols, mtry_max, F.get(), codes, n, binner, y_log10, y_fp.p, codes_p.p, d_train.p,
+                    queue.p, s);
     tuned = true;
   }
   const size_t per_wg = grow_scratch_bytes(n_cap, mtry_max, grow_has_wide_phase(cfg), grouped);

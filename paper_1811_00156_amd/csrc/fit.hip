@@ -1572,7 +1572,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC))) vo
 template <int BLOCK>
 const void* grow_kernel(bool wide, int occ) {
   constexpr bool G = AIWC_GROW_GROUPED != 0;
-  if (wide) return reinterpret_cast<const void*>(k_grow<BLOCK, true, 4, G>);
+  if constexpr (BLOCK < 192) {
+    // one- and two-wave workgroups serve deep queues of small trees only
+    if (wide) fail(AIWC_RF_EINVAL, "the workgroup-wide phase needs at least 192 threads per workgroup");
+  } else {
+    if (wide) return reinterpret_cast<const void*>(k_grow<BLOCK, true, 4, G>);
+  }
   switch (occ) {
     case 5: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 5, G>);
     case 6: return reinterpret_cast<const void*>(k_grow<BLOCK, false, 6, G>);
@@ -1582,6 +1587,8 @@ const void* grow_kernel(bool wide, int occ) {
 
 const void* grow_kernel_block(int block, bool wide, int occ) {
   switch (block) {
+    case 64: return grow_kernel<64>(wide, occ);
+    case 128: return grow_kernel<128>(wide, occ);
     case 192: return grow_kernel<192>(wide, occ);
     case 256: return grow_kernel<256>(wide, occ);
     case 512: return grow_kernel<512>(wide, occ);

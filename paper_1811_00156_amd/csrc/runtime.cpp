@@ -351,12 +351,14 @@ std::vector<GrowConfig> tune_candidates(const GrowConfig& base) {
   // set means no wide nodes, timed once per workgroup size at 4, 5 and 6 waves
   // per SIMD.  Where large-node tasks exist (limit above 64 rows) each shape is
   // timed with two and with four candidate columns per task.
+  // One- and two-wave workgroups are timed without wide nodes only.
   std::vector<GrowConfig> out;
-  for (int block : {192, 256, 512, 1024}) {
+  for (int block : {64, 128, 192, 256, 512, 1024}) {
     bool narrow_done = false;
     for (int h : {64, 512, 4096}) {
       const bool narrow = base.n_cap <= h;
       if (narrow && narrow_done) continue;
+      if (!narrow && block < 192) continue;
       narrow_done = narrow_done || narrow;
       for (int occ : {4, 5, 6}) {
         if (!narrow && occ != 4) continue;

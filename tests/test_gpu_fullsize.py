@@ -5,7 +5,7 @@
   one, and the whole forest's predictions of a seeded 20000-row subset.
 * The tuning grid on 2220 rows, 64 bins: 10 folds x mtry 1..34 x min.node.size
   {1,3,5,7,9} = 1700 forests x 256 trees in one fused graph launch at its
-  default shape (192 threads, 6 waves per SIMD, 4 columns per large-node task):
+  default shape (64 threads, 5 waves per SIMD, 4 columns per large-node task):
   a seeded subset of 50 forests tree for tree with their predictions, then
   every forest once.
 * Serving the 500-tree forest above: a Poisson stream of log-uniform requests
@@ -107,9 +107,10 @@ def oracle_grid_forest(oracle, grid, k):
 def test_grid_default_shape(grid):
     li = grid["forest"].launch()
     log(f"grid launch shape {li}")
-    # 435200 trees on 2000-row training sets: the shape every trees-per-CU-full
-    # grid takes (and the one the fused benchmark times unless it is tuned)
-    assert (li["block"], li["waves_per_simd"], li["big_cols"], li["wide_phase"], li["graph"]) == (192, 6, 4, 0, 1)
+    # 87040 task groups on 2000-row training sets: the shape of a grid whose
+    # queue holds at least 64 work items per CU (and the one the fused
+    # benchmark times unless it is tuned)
+    assert (li["block"], li["waves_per_simd"], li["big_cols"], li["wide_phase"], li["graph"]) == (64, 5, 4, 0, 1)
     # tree t of the five forests of each (fold, mtry) is one task group
     assert li["task_groups"] == 10 * 34 * 256
 

@@ -51,6 +51,22 @@ def test_shape_invariance(setup, block, huge_min):
         assert_tree_equal(tree, of.tree(t), f"block {block} huge_min {huge_min} tree {t}")
 
 
+@pytest.mark.parametrize("block", ["64", "128"])
+@pytest.mark.parametrize("occ", ["4", "5", "6"])
+def test_narrow_workgroup_invariance(setup, block, occ):
+    """One- and two-wave workgroups (the shapes of deep grid queues) grow the
+    same trees; they never take the workgroup-wide phase."""
+    rf, ds, ob, of = setup
+    log(f"shape block={block} occ={occ}")
+    f = fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_GROW_OCC": occ, "AIWC_RF_HUGE_MIN": "100000"})
+    li = f.launch()
+    assert (li["block"], li["waves_per_simd"], li["wide_phase"]) == (int(block), int(occ), 0)
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, of.tree(t), f"block {block} occ {occ} tree {t}")
+    with pytest.raises(rf.RFError):
+        fit_with(rf, ds, ob, {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_HUGE_MIN": "300"})
+
+
 def test_autotuned_fit_matches(setup):
     rf, ds, ob, of = setup
     f = fit_with(rf, ds, ob, {}, flags=rf.FIT_TUNE)
