@@ -174,7 +174,7 @@ class Binner:
     def n_bins(self) -> np.ndarray:
         return self.export()[0]
 
-    def __del__(self):
+    def __del__(self, _release=_release):  # (bound now: module globals may be gone at shutdown)
         _release(self, "aiwc_rf_binner_free")
 
 
@@ -267,7 +267,7 @@ class Forest:
             s += k
         return out
 
-    def __del__(self):
+    def __del__(self, _release=_release):  # (bound now: module globals may be gone at shutdown)
         _release(self, "aiwc_rf_forest_free")
 
 
