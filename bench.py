@@ -100,11 +100,11 @@ TRAFFIC_SOURCES = ["paper_1811_00156_amd/csrc/fit.hip", "paper_1811_00156_amd/cs
                    "paper_1811_00156_amd/csrc/internal.h"]
 
 
-def measured_traffic(kernel_key):
-    """HBM bytes per launch from the rocprofv3 counter runs summarised in
-    profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    the kernel, or the host code that picks its launch shape, has changed since
-    the counters were taken."""
+def profiled_record(kernel_key):
+    """The rocprofv3 counter figures of a grow-kernel instantiation summarised in
+    profiles/ (traffic.json: HBM bytes per launch from the byte-exact L2 request
+    counters, VALU wave-instructions per launch), or None when the kernel, or the
+    host code that picks its launch shape, has changed since they were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -120,7 +120,34 @@ def measured_traffic(kernel_key):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest()[:16] != rec["kernel_sha256_16"]:
         return None
-    return rec["traffic_bytes"]
+    return rec
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch (profiles/k_grow_traffic.txt), or None (see profiled_record)."""
+    rec = profiled_record(kernel_key)
+    return rec["traffic_bytes"] if rec else None
+
+
+# wave64 VALU instructions per second of the MI355X: 256 CUs x 4 SIMDs, each
+# issuing one VALU instruction per cycle at 2.4 GHz, a wave64 instruction
+# holding its 16-lane SIMD for 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def issue_roofline(kernel_key, ms):
+    """The grow kernel's VALU instruction issue rate against the chip's: the
+    profiled wave-instructions per launch (SQ_INSTS_VALU, profiles/
+    k_grow_shader_counters.txt) over this run's launch time; None when the
+    profile is stale."""
+    rec = profiled_record(kernel_key)
+    if not rec or "valu_wave_instructions" not in rec:
+        return None
+    n = float(rec["valu_wave_instructions"])
+    achieved = n / (ms / 1000.0)
+    return {"kernel": "k_grow", "bound": "valu_issue", "achieved": achieved, "unit": "wave64 VALU instructions/s",
+            "peak": VALU_ISSUE_PEAK, "frac": achieved / VALU_ISSUE_PEAK, "instructions_per_launch": n,
+            "source": "SQ_INSTS_VALU, profiles/k_grow_shader_counters.txt"}
 
 
 def lds_peak():
@@ -322,6 +349,7 @@ def bench_forest(args, wl_name):
     }
     if not args.no_lds:
         res["lds_roofline"] = lds_roofline(work[4], r["grow"], lds_peak())
+    res["issue_roofline"] = issue_roofline(f"k_grow@{wl_name}", r["grow"])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sample = {"c1": 100, "c2": 200, "c3": 16}.get(wl_name, 16)
@@ -423,6 +451,7 @@ def bench_grid(args):
     }
     if not args.no_lds:
         res["lds_roofline"] = lds_roofline(work[4], g_ms, lds_peak())
+    res["issue_roofline"] = issue_roofline("k_grow@c4", g_ms)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
@@ -467,6 +496,7 @@ def extra_legs(args):
           "lds_bin_adds": int(r["work"][4])}
     if not args.no_lds:
         c3["lds_roofline"] = lds_roofline(r["work"][4], r["grow"], lds_peak())
+    c3["issue_roofline"] = issue_roofline("k_grow@c3", r["grow"])
     log(f"c3: fit {r['fit']:.1f} ms, grow {r['grow']:.1f} ms, frac {c3['roofline']['frac']:.3f}")
     sv = serve_points(r["forest"], r["codes"].cpu().numpy(), ds.n, args.requests, load_fracs=(),
                       fixed_qps=(2000.0,))
