@@ -1175,6 +1175,7 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
 
   // threads that draw candidates each own a C-byte row of the LDS union area
   const int n_draw = min(BLOCK, (int)(a.union_bytes / (uint32_t)a.C));
+  const uint32_t draw_q = ((uint32_t)n_draw * (uint32_t)a.C + 15u) & ~15u;  // the draw queue, after the rows
   // (the member being grown, its min.node.size and node slot are kept in the
   // LDS, which spares registers across the level loop)
   uint32_t level_lo = 0, level_cnt = 1, next_id = 1;
@@ -1189,52 +1190,92 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
     if (!GROUPED || !sh.resume) {
     ++levels;
     // (a) leaf rules, candidate draws, tiers (the tier counts and the task
-    // queue head were reset before the level began)
+    // queue head were reset before the level began).  A one-wave workgroup
+    // queues its open nodes in the LDS after the draw rows (node and large-node
+    // index, 128 entries) and draws them 64 at a time, so that a level whose
+    // open nodes are sparse among its nodes runs the draws fewer times.
+    const bool queue_draws = BLOCK == kWave && n_draw == kWave && draw_q + 1024u <= a.union_bytes;
     if (tid < n_draw) {
       const int64_t min_node = GROUPED ? sh.vmin : (int64_t)T.min_node;
       // while the members' trees agree: an open node of at most the largest
       // member's min.node.size is a leaf for some members only
       const int64_t m_part = GROUPED && sh.vi < 0 ? (int64_t)sh.gmin[sh.gk - 1] : -1;
-      for (uint32_t k = tid; k < level_cnt; k += n_draw) {
-        const uint32_t N = x.mN[k];
-        const int64_t S = x.mS[k];
-        const uint64_t Q = x.mQ[k];
-        const uint32_t st = x.mstart[k];
-        const uint32_t len = x.mend[k] - st;
-        if ((int64_t)N <= min_node || node_is_pure(N, S, Q)) {
-          sc.status[k] = kLeaf;
-          continue;
+      uint32_t* const qk = reinterpret_cast<uint32_t*>(lds + draw_q);
+      uint32_t* const qj = qk + 128;
+      uint32_t q_head = 0, q_tail = 0;
+      auto draw_queued = [&](uint32_t n_q) {
+        if ((uint32_t)tid < n_q) {
+          const uint32_t e = (q_head + (uint32_t)tid) & 127u;
+          const uint32_t k = qk[e], j1 = qj[e];
+          draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                          sc.cand + (size_t)k * cand_stride(mtry), j1 ? sc.btask + (size_t)(j1 - 1) * mtry : nullptr,
+                          sh.nbins);
         }
-        if (GROUPED && (int64_t)N <= m_part) sh.part = 1u;
-        work_rows += len;
-        ++work_nodes;
-        // nodes above 32 rows add each row to an LDS bin per candidate column
-        if (len > 32) work_hist += (uint64_t)len * (uint64_t)mtry;
+        q_head += n_q;
+      };
+      const uint32_t k_end = queue_draws ? (level_cnt + kWave - 1) / kWave * kWave : level_cnt;
+      for (uint32_t k = tid; k < k_end; k += n_draw) {
+        bool open = false;
+        uint32_t j1 = 0;  // large node j: j + 1
         uint32_t* bt = nullptr;
-        if (len <= kSegMax) {
-          const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
-          sc.status[k] = kSmall;
-          NodeDesc* list = cls == 0   ? sc.seg[0]
-                           : cls == 1 ? sc.seg[1]
-                           : cls == 2 ? sc.seg[2]
-                           : cls == 3 ? sc.seg[3]
-                                      : sc.seg[4];
-          list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
-        } else if (!WIDE || (int32_t)len <= a.huge_min) {
-          sc.status[k] = kBig;
-          const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
-          sc.big[j] = NodeDesc{k, st, len, N, S};
-          sc.ridx[k] = j;
-          bt = sc.btask + (size_t)j * mtry;  // each (node, column) task's column and bin count
-        } else {
-          sc.status[k] = kHuge;
-          const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
-          sc.huge[h] = NodeDesc{k, st, len, N, S};
-          sc.ridx[k] = h;
+        if (k < level_cnt) {
+          const uint32_t N = x.mN[k];
+          const int64_t S = x.mS[k];
+          const uint64_t Q = x.mQ[k];
+          const uint32_t st = x.mstart[k];
+          const uint32_t len = x.mend[k] - st;
+          if ((int64_t)N <= min_node || node_is_pure(N, S, Q)) {
+            sc.status[k] = kLeaf;
+          } else {
+            open = true;
+            if (GROUPED && (int64_t)N <= m_part) sh.part = 1u;
+            work_rows += len;
+            ++work_nodes;
+            // nodes above 32 rows add each row to an LDS bin per candidate column
+            if (len > 32) work_hist += (uint64_t)len * (uint64_t)mtry;
+            if (len <= kSegMax) {
+              const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
+              sc.status[k] = kSmall;
+              NodeDesc* list = cls == 0   ? sc.seg[0]
+                               : cls == 1 ? sc.seg[1]
+                               : cls == 2 ? sc.seg[2]
+                               : cls == 3 ? sc.seg[3]
+                                          : sc.seg[4];
+              list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
+            } else if (!WIDE || (int32_t)len <= a.huge_min) {
+              sc.status[k] = kBig;
+              const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
+              sc.big[j] = NodeDesc{k, st, len, N, S};
+              sc.ridx[k] = j;
+              j1 = j + 1;
+              bt = sc.btask + (size_t)j * mtry;  // each (node, column) task's column and bin count
+            } else {
+              sc.status[k] = kHuge;
+              const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
+              sc.huge[h] = NodeDesc{k, st, len, N, S};
+              sc.ridx[k] = h;
+            }
+          }
         }
-        draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
-                        sc.cand + (size_t)k * cand_stride(mtry), bt, sh.nbins);
+        if (queue_draws) {
+          const uint64_t om = __ballot(open);
+          if (open) {
+            const uint32_t e = (q_tail + (uint32_t)__popcll(om & ((1ull << lane) - 1ull))) & 127u;
+            qk[e] = k;
+            qj[e] = j1;
+          }
+          q_tail += (uint32_t)__popcll(om);
+          wave_lds_sync();
+          if (q_tail - q_head >= (uint32_t)kWave) {
+            draw_queued(kWave);
+            wave_lds_sync();
+          }
+        } else if (open) {
+          draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                          sc.cand + (size_t)k * cand_stride(mtry), bt, sh.nbins);
+        }
       }
+      if (queue_draws && q_tail > q_head) draw_queued(q_tail - q_head);
     }
     __syncthreads();
     const uint32_t n_big = sh.cnt[1], n_huge = sh.cnt[2];
