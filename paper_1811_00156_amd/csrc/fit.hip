@@ -1182,402 +1182,402 @@ __device__ __forceinline__ void grow_group(const GrowArgs& a, const TreeTask& T,
   int cur = 0;
   uint64_t work_rows = 0, work_nodes = 0, work_part = 0, levels = 0, work_hist = 0;
   for (;;) {
-  while (level_cnt > 0) {
-    const Level2 C = cur ? sc.L1 : sc.L0;  // this level
-    const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
-    const Ctx x{&a, &T, sc, C.buf, X.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
-    // (a) - (c) are skipped by a member that grows on from the parting level
-    if (!GROUPED || !sh.resume) {
-    ++levels;
-    // (a) leaf rules, candidate draws, tiers (the tier counts and the task
-    // queue head were reset before the level began).  A one-wave workgroup
-    // queues its open nodes in the LDS after the draw rows (node and large-node
-    // index, 128 entries) and draws them 64 at a time, so that a level whose
-    // open nodes are sparse among its nodes runs the draws fewer times.
-    const bool queue_draws = BLOCK == kWave && n_draw == kWave && draw_q + 1024u <= a.union_bytes;
-    if (tid < n_draw) {
-      const int64_t min_node = GROUPED ? sh.vmin : (int64_t)T.min_node;
-      // while the members' trees agree: an open node of at most the largest
-      // member's min.node.size is a leaf for some members only
-      const int64_t m_part = GROUPED && sh.vi < 0 ? (int64_t)sh.gmin[sh.gk - 1] : -1;
-      uint32_t* const qk = reinterpret_cast<uint32_t*>(lds + draw_q);
-      uint32_t* const qj = qk + 128;
-      uint32_t q_head = 0, q_tail = 0;
-      auto draw_queued = [&](uint32_t n_q) {
-        if ((uint32_t)tid < n_q) {
-          const uint32_t e = (q_head + (uint32_t)tid) & 127u;
-          const uint32_t k = qk[e], j1 = qj[e];
-          draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
-                          sc.cand + (size_t)k * cand_stride(mtry), j1 ? sc.btask + (size_t)(j1 - 1) * mtry : nullptr,
-                          sh.nbins);
-        }
-        q_head += n_q;
-      };
-      const uint32_t k_end = queue_draws ? (level_cnt + kWave - 1) / kWave * kWave : level_cnt;
-      for (uint32_t k = tid; k < k_end; k += n_draw) {
-        bool open = false;
-        uint32_t j1 = 0;  // large node j: j + 1
-        uint32_t* bt = nullptr;
-        if (k < level_cnt) {
-          const uint32_t N = x.mN[k];
-          const int64_t S = x.mS[k];
-          const uint64_t Q = x.mQ[k];
-          const uint32_t st = x.mstart[k];
-          const uint32_t len = x.mend[k] - st;
-          if ((int64_t)N <= min_node || node_is_pure(N, S, Q)) {
-            sc.status[k] = kLeaf;
-          } else {
-            open = true;
-            if (GROUPED && (int64_t)N <= m_part) sh.part = 1u;
-            work_rows += len;
-            ++work_nodes;
-            // nodes above 32 rows add each row to an LDS bin per candidate column
-            if (len > 32) work_hist += (uint64_t)len * (uint64_t)mtry;
-            if (len <= kSegMax) {
-              const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
-              sc.status[k] = kSmall;
-              NodeDesc* list = cls == 0   ? sc.seg[0]
-                               : cls == 1 ? sc.seg[1]
-                               : cls == 2 ? sc.seg[2]
-                               : cls == 3 ? sc.seg[3]
-                                          : sc.seg[4];
-              list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
-            } else if (!WIDE || (int32_t)len <= a.huge_min) {
-              sc.status[k] = kBig;
-              const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
-              sc.big[j] = NodeDesc{k, st, len, N, S};
-              sc.ridx[k] = j;
-              j1 = j + 1;
-              bt = sc.btask + (size_t)j * mtry;  // each (node, column) task's column and bin count
-            } else {
-              sc.status[k] = kHuge;
-              const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
-              sc.huge[h] = NodeDesc{k, st, len, N, S};
-              sc.ridx[k] = h;
+    while (level_cnt > 0) {
+      const Level2 C = cur ? sc.L1 : sc.L0;  // this level
+      const Level2 X = cur ? sc.L0 : sc.L1;  // the next level
+      const Ctx x{&a, &T, sc, C.buf, X.buf, C.mstart, C.mend, C.mN, C.mS, C.mQ};
+      // (a) - (c) are skipped by a member that grows on from the parting level
+      if (!GROUPED || !sh.resume) {
+        ++levels;
+        // (a) leaf rules, candidate draws, tiers (the tier counts and the task
+        // queue head were reset before the level began).  A one-wave workgroup
+        // queues its open nodes in the LDS after the draw rows (node and large-node
+        // index, 128 entries) and draws them 64 at a time, so that a level whose
+        // open nodes are sparse among its nodes runs the draws fewer times.
+        const bool queue_draws = BLOCK == kWave && n_draw == kWave && draw_q + 1024u <= a.union_bytes;
+        if (tid < n_draw) {
+          const int64_t min_node = GROUPED ? sh.vmin : (int64_t)T.min_node;
+          // while the members' trees agree: an open node of at most the largest
+          // member's min.node.size is a leaf for some members only
+          const int64_t m_part = GROUPED && sh.vi < 0 ? (int64_t)sh.gmin[sh.gk - 1] : -1;
+          uint32_t* const qk = reinterpret_cast<uint32_t*>(lds + draw_q);
+          uint32_t* const qj = qk + 128;
+          uint32_t q_head = 0, q_tail = 0;
+          auto draw_queued = [&](uint32_t n_q) {
+            if ((uint32_t)tid < n_q) {
+              const uint32_t e = (q_head + (uint32_t)tid) & 127u;
+              const uint32_t k = qk[e], j1 = qj[e];
+              draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                              sc.cand + (size_t)k * cand_stride(mtry), j1 ? sc.btask + (size_t)(j1 - 1) * mtry : nullptr,
+                              sh.nbins);
+            }
+            q_head += n_q;
+          };
+          const uint32_t k_end = queue_draws ? (level_cnt + kWave - 1) / kWave * kWave : level_cnt;
+          for (uint32_t k = tid; k < k_end; k += n_draw) {
+            bool open = false;
+            uint32_t j1 = 0;  // large node j: j + 1
+            uint32_t* bt = nullptr;
+            if (k < level_cnt) {
+              const uint32_t N = x.mN[k];
+              const int64_t S = x.mS[k];
+              const uint64_t Q = x.mQ[k];
+              const uint32_t st = x.mstart[k];
+              const uint32_t len = x.mend[k] - st;
+              if ((int64_t)N <= min_node || node_is_pure(N, S, Q)) {
+                sc.status[k] = kLeaf;
+              } else {
+                open = true;
+                if (GROUPED && (int64_t)N <= m_part) sh.part = 1u;
+                work_rows += len;
+                ++work_nodes;
+                // nodes above 32 rows add each row to an LDS bin per candidate column
+                if (len > 32) work_hist += (uint64_t)len * (uint64_t)mtry;
+                if (len <= kSegMax) {
+                  const int cls = len <= 4 ? 0 : len <= 8 ? 1 : len <= 16 ? 2 : len <= 32 ? 3 : 4;
+                  sc.status[k] = kSmall;
+                  NodeDesc* list = cls == 0   ? sc.seg[0]
+                                   : cls == 1 ? sc.seg[1]
+                                   : cls == 2 ? sc.seg[2]
+                                   : cls == 3 ? sc.seg[3]
+                                              : sc.seg[4];
+                  list[atomicAdd(&sh.cnt[3 + cls], 1u)] = NodeDesc{k, st, len, N, S};
+                } else if (!WIDE || (int32_t)len <= a.huge_min) {
+                  sc.status[k] = kBig;
+                  const uint32_t j = atomicAdd(&sh.cnt[1], 1u);
+                  sc.big[j] = NodeDesc{k, st, len, N, S};
+                  sc.ridx[k] = j;
+                  j1 = j + 1;
+                  bt = sc.btask + (size_t)j * mtry;  // each (node, column) task's column and bin count
+                } else {
+                  sc.status[k] = kHuge;
+                  const uint32_t h = atomicAdd(&sh.cnt[2], 1u);
+                  sc.huge[h] = NodeDesc{k, st, len, N, S};
+                  sc.ridx[k] = h;
+                }
+              }
+            }
+            if (queue_draws) {
+              const uint64_t om = __ballot(open);
+              if (open) {
+                const uint32_t e = (q_tail + (uint32_t)__popcll(om & ((1ull << lane) - 1ull))) & 127u;
+                qk[e] = k;
+                qj[e] = j1;
+              }
+              q_tail += (uint32_t)__popcll(om);
+              wave_lds_sync();
+              if (q_tail - q_head >= (uint32_t)kWave) {
+                draw_queued(kWave);
+                wave_lds_sync();
+              }
+            } else if (open) {
+              draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
+                              sc.cand + (size_t)k * cand_stride(mtry), bt, sh.nbins);
             }
           }
+          if (queue_draws && q_tail > q_head) draw_queued(q_tail - q_head);
         }
-        if (queue_draws) {
-          const uint64_t om = __ballot(open);
-          if (open) {
-            const uint32_t e = (q_tail + (uint32_t)__popcll(om & ((1ull << lane) - 1ull))) & 127u;
-            qk[e] = k;
-            qj[e] = j1;
+        __syncthreads();
+        const uint32_t n_big = sh.cnt[1], n_huge = sh.cnt[2];
+        // (b) wide nodes, in batches, with the whole workgroup
+        if (WIDE && n_huge > 0) {
+          const int per_node = mtry * a.bstride * 8;
+          int nb = 1, hc = mtry;
+          if (per_node <= (int)a.union_bytes)
+            nb = min(min(kWideMax, 256 / ((mtry + 7) & ~7)), (int)a.union_bytes / per_node);
+          // (records of wide node j go after the large nodes', at n_big + j)
+          else  // column chunks of a multiple of 8 (the LDS holds at least 8 columns)
+            hc = max(8, (int)a.union_bytes / (a.bstride * 8) / 8 * 8);
+          wide_phase<BLOCK>(x, sc.huge, n_huge, nb, hc, n_big, lds, sh);
+        }
+        // (c) large-node columns and small-node segments, one wave each; a wave
+        // takes its next task from the queue head when it starts one (their costs
+        // differ widely, so a fixed deal would leave waves idle at the barrier)
+        {
+          const uint32_t per_big = (uint32_t)((mtry + a.big_cols - 1) / a.big_cols);
+          const uint32_t n_big_tasks = n_big * per_big;
+          uint32_t first[kSegClasses + 1];
+          first[0] = n_big_tasks;
+          for (int c = 0; c < kSegClasses; ++c) {
+            const uint32_t per_wave = (uint32_t)(kWave >> (2 + c));
+            first[c + 1] = first[c] + (sh.cnt[3 + c] + per_wave - 1) / per_wave;
           }
-          q_tail += (uint32_t)__popcll(om);
-          wave_lds_sync();
-          if (q_tail - q_head >= (uint32_t)kWave) {
-            draw_queued(kWave);
-            wave_lds_sync();
+          WaveHist& wl = *reinterpret_cast<WaveHist*>(lds + (size_t)wid * a.wave_bytes);
+          for (uint32_t t = wid; t < first[kSegClasses];) {
+            uint32_t t_next = 0;
+            if (lane == 0) t_next = atomicAdd(&sh.next_task, 1u);
+            if (t < n_big_tasks)
+              big_task(x, t / per_big, (int)(t % per_big) * a.big_cols, wl);
+            else if (t < first[1])
+              small_task<4>(x, sc.seg[0], t - first[0], sh.cnt[3], wl);
+            else if (t < first[2])
+              small_task<8>(x, sc.seg[1], t - first[1], sh.cnt[4], wl);
+            else if (t < first[3])
+              small_task<16>(x, sc.seg[2], t - first[2], sh.cnt[5], wl);
+            else if (t < first[4])
+              small_task<32>(x, sc.seg[3], t - first[3], sh.cnt[6], wl);
+            else
+              rank_task(x, sc.seg[4], t - first[4], sh.cnt[7], wl);
+            t = read_lane(t_next, 0);
           }
-        } else if (open) {
-          draw_candidates(lds + tid, n_draw, T.seed, level_lo + k, (uint32_t)T.tree, a.C, mtry,
-                          sc.cand + (size_t)k * cand_stride(mtry), bt, sh.nbins);
+        }
+        __syncthreads();
+        if (GROUPED && sh.part) {
+          // the members' trees part at this level: put its searched state aside
+          // (the open nodes' entries lie in [0, n_inbag)); the first member goes on
+          const uint32_t ni = sh.n_inbag;
+          for (uint32_t i = tid; i < ni; i += BLOCK) {
+            sc.SN.L.buf[i] = C.buf[i];
+            sc.SN.nbuf[i] = X.buf[i];
+          }
+          for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
+            sc.SN.L.mstart[k] = C.mstart[k];
+            sc.SN.L.mend[k] = C.mend[k];
+            sc.SN.L.mN[k] = C.mN[k];
+            sc.SN.L.mS[k] = C.mS[k];
+            sc.SN.L.mQ[k] = C.mQ[k];
+            sc.SN.status[k] = sc.status[k];
+            sc.SN.ridx[k] = sc.ridx[k];
+            sc.SN.dcol[k] = sc.dcol[k];
+            sc.SN.dbin[k] = sc.dbin[k];
+            sc.SN.dNL[k] = sc.dNL[k];
+            sc.SN.dSL[k] = sc.dSL[k];
+            sc.SN.dcnt[k] = sc.dcnt[k];
+            sc.SN.dQL[k] = sc.dQL[k];
+          }
+          for (uint32_t i = tid; i < (n_big + n_huge) * (uint32_t)mtry; i += BLOCK) sc.SN.recs[i] = sc.recs[i];
+          if (WIDE && n_huge > 0) {
+            const uint4* src = reinterpret_cast<const uint4*>(sc.side);
+            uint4* dst = reinterpret_cast<uint4*>(sc.SN.side);
+            for (uint32_t i = tid; i < ni * (uint32_t)cand_stride(mtry) / 16u; i += BLOCK) dst[i] = src[i];
+          }
+          __syncthreads();  // (every thread has read the flag)
+          if (tid == 0) {
+            sh.part = 0;
+            sh.vi = 0;
+            sh.f_lo = level_lo;
+            sh.f_cnt = level_cnt;
+            sh.f_next = next_id;
+            sh.f_cur = (uint32_t)cur;
+            sh.f_levels = (uint32_t)levels;
+            sh.f_big = n_big;
+            sh.f_huge = n_huge;
+          }
         }
       }
-      if (queue_draws && q_tail > q_head) draw_queued(q_tail - q_head);
+      const uint32_t n_big = sh.cnt[1];
+      // (d) the large and wide nodes' decisions from their records (the wide
+      // nodes' records follow the large nodes'), then (e) breadth-first child
+      // ids, node words, children's sums and cursors, and the partition's chunks
+      // of 64 entries of every split node that is not placed yet.  The cursors
+      // live in the LDS union area (free until the next level) when the level's
+      // nodes fit it, else in scratch.
+      const bool lds_cur = level_cnt <= a.union_bytes / (uint32_t)sizeof(Cursor);
+      const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
+      Cursor* lcur = reinterpret_cast<Cursor*>(lds);
+      uint32_t n_split = 0, n_chunks = 0;
+      for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
+        const uint32_t k = b0 + tid;
+        const bool in = k < level_cnt;
+        uint8_t stk = in ? sc.status[k] : kLeaf;
+        Decision dc{false, 0u, 0u, 0u, 0, 0u};
+        // a wide node's rows carry their candidate codes (candidate index + 1 in
+        // the partition's chunk word; 0 = read the row's code)
+        uint32_t side_ci = 0;
+        if (stk == kBig || stk == kHuge) {
+          const uint32_t ri = sc.ridx[k] + (stk == kHuge ? n_big : 0u);
+          dc = decide_from_recs(sc.recs + (size_t)ri * mtry, mtry, x.mS[k], x.mN[k]);
+          if (WIDE && stk == kHuge) side_ci = dc.cand + 1u;
+          stk = dc.split ? kSplit : kLeaf;
+        } else if (stk == kSplitDone) {
+          dc = Decision{true, sc.dcol[k], sc.dbin[k], sc.dNL[k], sc.dSL[k], 0u};
+        }
+        const bool split = stk == kSplit || stk == kSplitDone;
+        // (the small nodes' rows were placed by their searches)
+        const uint32_t nch = stk == kSplit ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
+        // split ranks in the low half, chunk offsets in the high half
+        uint64_t tot;
+        const uint64_t ex = block_exscan64<BLOCK>((split ? 1ull : 0ull) | ((uint64_t)nch << 32), sh.tmp64, tot);
+        const uint32_t total = (uint32_t)tot, ctotal = (uint32_t)(tot >> 32);
+        const uint32_t r = (uint32_t)ex + n_split;
+        const uint32_t cfirst = (uint32_t)(ex >> 32) + n_chunks;
+        // (the bounds below hold by construction; the guards keep a broken
+        // invariant from writing outside the scratch arrays)
+        if (nch > 0 && (uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2)) {
+          const uint32_t st = x.mstart[k], en = x.mend[k], cb = dc.col | (dc.bin << 8) | (side_ci << 16);
+          for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint4(st + c * kWave, en, r, cb);
+        }
+        if (in) {
+          const uint32_t node = level_lo + k;
+          const uint32_t N = x.mN[k];
+          const int64_t S = x.mS[k];
+          if (split && (int64_t)2 * r + 1 >= a.n_cap) {
+            atomicOr(a.status, kStatusCapacity);
+          } else if (split) {
+            const uint32_t left = next_id + 2 * r;
+            if ((int64_t)left + 1 < T.capacity) {
+              a.nodes[base_node + node] = node_split(dc.col, dc.bin, left);
+            } else {
+              atomicOr(a.status, kStatusCapacity);
+            }
+            const uint32_t st = x.mstart[k], en = x.mend[k];
+            work_part += en - st;
+            // a placed node's boundary is known; its cursor is marked done
+            const bool done = stk == kSplitDone;
+            const Cursor c0{done ? 0xFFFFFFFFu : st, en, 0ull};
+            if (lds_cur)
+              lcur[r] = c0;
+            else
+              sc.cur[r] = c0;
+            if (done) {
+              const uint32_t b = st + sc.dcnt[k];
+              const uint64_t QL = sc.dQL[k];
+              X.mend[2 * r] = b;
+              X.mstart[2 * r + 1] = b;
+              X.mQ[2 * r] = QL;
+            }
+            const uint32_t NL = dc.NL;
+            const int64_t SL = dc.SL;
+            X.mstart[2 * r] = st;
+            X.mN[2 * r] = NL;
+            X.mS[2 * r] = SL;
+            X.mend[2 * r + 1] = en;
+            X.mN[2 * r + 1] = N - NL;
+            X.mS[2 * r + 1] = S - SL;
+            // the right side's: the parent's, less the left side's when known
+            X.mQ[2 * r + 1] = x.mQ[k] - (done ? sc.dQL[k] : 0ull);
+          } else {
+            a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
+          }
+          a.node_N[base_node + node] = N;
+        }
+        n_split += total;
+        n_chunks += ctotal;
+      }
+      __syncthreads();
+      if ((int64_t)next_id + 2 * (int64_t)n_split > T.capacity ||
+          (int64_t)n_chunks > a.n_cap / 64 + a.n_cap / 2 + 2) {
+        // cannot happen for consistent inputs: every child holds an in-bag row
+        if (tid == 0) atomicOr(a.status, kStatusCapacity);
+        next_id = (uint32_t)T.capacity;
+        break;
+      }
+      // (f) partition the entries of split nodes into their children's segments
+      if (lds_cur)
+        partition_level<BLOCK, WIDE>(x, X.buf, lcur, n_chunks);
+      else
+        partition_level<BLOCK, WIDE>(x, X.buf, sc.cur, n_chunks);
+      __syncthreads();
+      // (g) the boundary between each pair of children, and their sums of w y^2
+      for (uint32_t r = tid; r < n_split; r += BLOCK) {
+        const Cursor c = lds_cur ? lcur[r] : sc.cur[r];
+        if (c.L == 0xFFFFFFFFu) continue;  // placed by its search
+        X.mend[2 * r] = c.L;
+        X.mstart[2 * r + 1] = c.L;
+        X.mQ[2 * r] = c.q;
+        X.mQ[2 * r + 1] -= c.q;
+      }
+      // the next level's tier counts and task queue head
+      if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
+      if (tid == 0) {
+        sh.next_task = NW;
+        if (GROUPED) sh.resume = 0;
+      }
+      __syncthreads();
+      level_lo = next_id;
+      level_cnt = 2 * n_split;
+      next_id += 2 * n_split;
+      cur ^= 1;
     }
-    __syncthreads();
-    const uint32_t n_big = sh.cnt[1], n_huge = sh.cnt[2];
-    // (b) wide nodes, in batches, with the whole workgroup
-    if (WIDE && n_huge > 0) {
-      const int per_node = mtry * a.bstride * 8;
-      int nb = 1, hc = mtry;
-      if (per_node <= (int)a.union_bytes)
-        nb = min(min(kWideMax, 256 / ((mtry + 7) & ~7)), (int)a.union_bytes / per_node);
-      // (records of wide node j go after the large nodes', at n_big + j)
-      else  // column chunks of a multiple of 8 (the LDS holds at least 8 columns)
-        hc = max(8, (int)a.union_bytes / (a.bstride * 8) / 8 * 8);
-      wide_phase<BLOCK>(x, sc.huge, n_huge, nb, hc, n_big, lds, sh);
+    // the tree of member max(vi, 0) is complete
+    work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
+    work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, sh.red);
+    work_part = block_sum<BLOCK, uint64_t>(work_part, sh.red);
+    work_hist = block_sum<BLOCK, uint64_t>(work_hist, sh.red);
+    const int vi = GROUPED ? sh.vi : 0, K = GROUPED ? sh.gk : 1;
+    const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
+    const int v0 = vi < 0 ? 0 : vi;
+    // without a parting level every member's tree is the first one's
+    const int v1 = vi < 0 ? K : vi + 1;
+    for (int v = v0; v < v1; ++v) {
+      if (v > v0) {
+        const int64_t b = sh.gbase[v];
+        for (uint32_t i = tid; i < next_id; i += BLOCK) {
+          a.nodes[b + i] = a.nodes[base_node + i];
+          a.node_N[b + i] = a.node_N[base_node + i];
+        }
+      }
+      if (tid == 0) {
+        const int64_t ti = GROUPED ? sh.gtask[v] : sh.gtask[0];
+        a.n_nodes[ti] = (int32_t)next_id;
+        int64_t* wk = a.work + kWorkWords * ti;
+        const bool first = v == v0;
+        wk[0] = first ? (int64_t)work_rows : 0;
+        wk[1] = first ? (int64_t)work_nodes : 0;
+        wk[2] = first ? (int64_t)work_part : 0;
+        wk[3] = (int64_t)levels;
+        wk[4] = first ? (int64_t)work_hist : 0;
+      }
     }
-    // (c) large-node columns and small-node segments, one wave each; a wave
-    // takes its next task from the queue head when it starts one (their costs
-    // differ widely, so a fixed deal would leave waves idle at the barrier)
+    if (vi < 0 || vi + 1 == K) break;
+    // member vi + 1 grows on from the parting level's decisions: its searched
+    // state restored, the nodes of at most its min.node.size made leaves, the
+    // shared levels' node words copied into its slot
+    const int64_t nbase = sh.gbase[vi + 1], m_v = sh.gmin[vi + 1];
+    level_lo = sh.f_lo;
+    level_cnt = sh.f_cnt;
+    next_id = sh.f_next;
+    cur = (int)sh.f_cur;
+    levels = sh.f_levels;
+    work_rows = work_nodes = work_part = work_hist = 0;
     {
-      const uint32_t per_big = (uint32_t)((mtry + a.big_cols - 1) / a.big_cols);
-      const uint32_t n_big_tasks = n_big * per_big;
-      uint32_t first[kSegClasses + 1];
-      first[0] = n_big_tasks;
-      for (int c = 0; c < kSegClasses; ++c) {
-        const uint32_t per_wave = (uint32_t)(kWave >> (2 + c));
-        first[c + 1] = first[c] + (sh.cnt[3 + c] + per_wave - 1) / per_wave;
+      const uint32_t f_big = sh.f_big, f_huge = sh.f_huge;
+      const int64_t b0 = sh.gbase[0];
+      for (uint32_t i = tid; i < level_lo; i += BLOCK) {
+        a.nodes[nbase + i] = a.nodes[b0 + i];
+        a.node_N[nbase + i] = a.node_N[b0 + i];
       }
-      WaveHist& wl = *reinterpret_cast<WaveHist*>(lds + (size_t)wid * a.wave_bytes);
-      for (uint32_t t = wid; t < first[kSegClasses];) {
-        uint32_t t_next = 0;
-        if (lane == 0) t_next = atomicAdd(&sh.next_task, 1u);
-        if (t < n_big_tasks)
-          big_task(x, t / per_big, (int)(t % per_big) * a.big_cols, wl);
-        else if (t < first[1])
-          small_task<4>(x, sc.seg[0], t - first[0], sh.cnt[3], wl);
-        else if (t < first[2])
-          small_task<8>(x, sc.seg[1], t - first[1], sh.cnt[4], wl);
-        else if (t < first[3])
-          small_task<16>(x, sc.seg[2], t - first[2], sh.cnt[5], wl);
-        else if (t < first[4])
-          small_task<32>(x, sc.seg[3], t - first[3], sh.cnt[6], wl);
-        else
-          rank_task(x, sc.seg[4], t - first[4], sh.cnt[7], wl);
-        t = read_lane(t_next, 0);
-      }
-    }
-    __syncthreads();
-    if (GROUPED && sh.part) {
-      // the members' trees part at this level: put its searched state aside
-      // (the open nodes' entries lie in [0, n_inbag)); the first member goes on
+      const Level2 C = cur ? sc.L1 : sc.L0;
+      const Level2 X = cur ? sc.L0 : sc.L1;
       const uint32_t ni = sh.n_inbag;
       for (uint32_t i = tid; i < ni; i += BLOCK) {
-        sc.SN.L.buf[i] = C.buf[i];
-        sc.SN.nbuf[i] = X.buf[i];
+        C.buf[i] = sc.SN.L.buf[i];
+        X.buf[i] = sc.SN.nbuf[i];
       }
       for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-        sc.SN.L.mstart[k] = C.mstart[k];
-        sc.SN.L.mend[k] = C.mend[k];
-        sc.SN.L.mN[k] = C.mN[k];
-        sc.SN.L.mS[k] = C.mS[k];
-        sc.SN.L.mQ[k] = C.mQ[k];
-        sc.SN.status[k] = sc.status[k];
-        sc.SN.ridx[k] = sc.ridx[k];
-        sc.SN.dcol[k] = sc.dcol[k];
-        sc.SN.dbin[k] = sc.dbin[k];
-        sc.SN.dNL[k] = sc.dNL[k];
-        sc.SN.dSL[k] = sc.dSL[k];
-        sc.SN.dcnt[k] = sc.dcnt[k];
-        sc.SN.dQL[k] = sc.dQL[k];
+        const uint32_t N = sc.SN.L.mN[k];
+        C.mstart[k] = sc.SN.L.mstart[k];
+        C.mend[k] = sc.SN.L.mend[k];
+        C.mN[k] = N;
+        C.mS[k] = sc.SN.L.mS[k];
+        C.mQ[k] = sc.SN.L.mQ[k];
+        const uint8_t st = sc.SN.status[k];
+        sc.status[k] = (int64_t)N <= m_v ? kLeaf : st;
+        sc.ridx[k] = sc.SN.ridx[k];
+        sc.dcol[k] = sc.SN.dcol[k];
+        sc.dbin[k] = sc.SN.dbin[k];
+        sc.dNL[k] = sc.SN.dNL[k];
+        sc.dSL[k] = sc.SN.dSL[k];
+        sc.dcnt[k] = sc.SN.dcnt[k];
+        sc.dQL[k] = sc.SN.dQL[k];
       }
-      for (uint32_t i = tid; i < (n_big + n_huge) * (uint32_t)mtry; i += BLOCK) sc.SN.recs[i] = sc.recs[i];
-      if (WIDE && n_huge > 0) {
-        const uint4* src = reinterpret_cast<const uint4*>(sc.side);
-        uint4* dst = reinterpret_cast<uint4*>(sc.SN.side);
+      for (uint32_t i = tid; i < (f_big + f_huge) * (uint32_t)mtry; i += BLOCK) sc.recs[i] = sc.SN.recs[i];
+      if (WIDE && f_huge > 0) {
+        const uint4* src = reinterpret_cast<const uint4*>(sc.SN.side);
+        uint4* dst = reinterpret_cast<uint4*>(sc.side);
         for (uint32_t i = tid; i < ni * (uint32_t)cand_stride(mtry) / 16u; i += BLOCK) dst[i] = src[i];
       }
-      __syncthreads();  // (every thread has read the flag)
-      if (tid == 0) {
-        sh.part = 0;
-        sh.vi = 0;
-        sh.f_lo = level_lo;
-        sh.f_cnt = level_cnt;
-        sh.f_next = next_id;
-        sh.f_cur = (uint32_t)cur;
-        sh.f_levels = (uint32_t)levels;
-        sh.f_big = n_big;
-        sh.f_huge = n_huge;
-      }
+      __syncthreads();  // (every thread has read the member index)
+      if (tid < 3 + kSegClasses) sh.cnt[tid] = tid == 1 ? f_big : tid == 2 ? f_huge : 0u;
     }
-    }
-    const uint32_t n_big = sh.cnt[1];
-    // (d) the large and wide nodes' decisions from their records (the wide
-    // nodes' records follow the large nodes'), then (e) breadth-first child
-    // ids, node words, children's sums and cursors, and the partition's chunks
-    // of 64 entries of every split node that is not placed yet.  The cursors
-    // live in the LDS union area (free until the next level) when the level's
-    // nodes fit it, else in scratch.
-    const bool lds_cur = level_cnt <= a.union_bytes / (uint32_t)sizeof(Cursor);
-    const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
-    Cursor* lcur = reinterpret_cast<Cursor*>(lds);
-    uint32_t n_split = 0, n_chunks = 0;
-    for (uint32_t b0 = 0; b0 < level_cnt; b0 += BLOCK) {
-      const uint32_t k = b0 + tid;
-      const bool in = k < level_cnt;
-      uint8_t stk = in ? sc.status[k] : kLeaf;
-      Decision dc{false, 0u, 0u, 0u, 0, 0u};
-      // a wide node's rows carry their candidate codes (candidate index + 1 in
-      // the partition's chunk word; 0 = read the row's code)
-      uint32_t side_ci = 0;
-      if (stk == kBig || stk == kHuge) {
-        const uint32_t ri = sc.ridx[k] + (stk == kHuge ? n_big : 0u);
-        dc = decide_from_recs(sc.recs + (size_t)ri * mtry, mtry, x.mS[k], x.mN[k]);
-        if (WIDE && stk == kHuge) side_ci = dc.cand + 1u;
-        stk = dc.split ? kSplit : kLeaf;
-      } else if (stk == kSplitDone) {
-        dc = Decision{true, sc.dcol[k], sc.dbin[k], sc.dNL[k], sc.dSL[k], 0u};
-      }
-      const bool split = stk == kSplit || stk == kSplitDone;
-      // (the small nodes' rows were placed by their searches)
-      const uint32_t nch = stk == kSplit ? (x.mend[k] - x.mstart[k] + kWave - 1) / kWave : 0u;
-      // split ranks in the low half, chunk offsets in the high half
-      uint64_t tot;
-      const uint64_t ex = block_exscan64<BLOCK>((split ? 1ull : 0ull) | ((uint64_t)nch << 32), sh.tmp64, tot);
-      const uint32_t total = (uint32_t)tot, ctotal = (uint32_t)(tot >> 32);
-      const uint32_t r = (uint32_t)ex + n_split;
-      const uint32_t cfirst = (uint32_t)(ex >> 32) + n_chunks;
-      // (the bounds below hold by construction; the guards keep a broken
-      // invariant from writing outside the scratch arrays)
-      if (nch > 0 && (uint64_t)cfirst + nch <= (uint64_t)(a.n_cap / 64 + a.n_cap / 2 + 2)) {
-        const uint32_t st = x.mstart[k], en = x.mend[k], cb = dc.col | (dc.bin << 8) | (side_ci << 16);
-        for (uint32_t c = 0; c < nch; ++c) sc.chunks[cfirst + c] = make_uint4(st + c * kWave, en, r, cb);
-      }
-      if (in) {
-        const uint32_t node = level_lo + k;
-        const uint32_t N = x.mN[k];
-        const int64_t S = x.mS[k];
-        if (split && (int64_t)2 * r + 1 >= a.n_cap) {
-          atomicOr(a.status, kStatusCapacity);
-        } else if (split) {
-          const uint32_t left = next_id + 2 * r;
-          if ((int64_t)left + 1 < T.capacity) {
-            a.nodes[base_node + node] = node_split(dc.col, dc.bin, left);
-          } else {
-            atomicOr(a.status, kStatusCapacity);
-          }
-          const uint32_t st = x.mstart[k], en = x.mend[k];
-          work_part += en - st;
-          // a placed node's boundary is known; its cursor is marked done
-          const bool done = stk == kSplitDone;
-          const Cursor c0{done ? 0xFFFFFFFFu : st, en, 0ull};
-          if (lds_cur)
-            lcur[r] = c0;
-          else
-            sc.cur[r] = c0;
-          if (done) {
-            const uint32_t b = st + sc.dcnt[k];
-            const uint64_t QL = sc.dQL[k];
-            X.mend[2 * r] = b;
-            X.mstart[2 * r + 1] = b;
-            X.mQ[2 * r] = QL;
-          }
-          const uint32_t NL = dc.NL;
-          const int64_t SL = dc.SL;
-          X.mstart[2 * r] = st;
-          X.mN[2 * r] = NL;
-          X.mS[2 * r] = SL;
-          X.mend[2 * r + 1] = en;
-          X.mN[2 * r + 1] = N - NL;
-          X.mS[2 * r + 1] = S - SL;
-          // the right side's: the parent's, less the left side's when known
-          X.mQ[2 * r + 1] = x.mQ[k] - (done ? sc.dQL[k] : 0ull);
-        } else {
-          a.nodes[base_node + node] = node_leaf(leaf_value(N, S));
-        }
-        a.node_N[base_node + node] = N;
-      }
-      n_split += total;
-      n_chunks += ctotal;
-    }
-    __syncthreads();
-    if ((int64_t)next_id + 2 * (int64_t)n_split > T.capacity ||
-        (int64_t)n_chunks > a.n_cap / 64 + a.n_cap / 2 + 2) {
-      // cannot happen for consistent inputs: every child holds an in-bag row
-      if (tid == 0) atomicOr(a.status, kStatusCapacity);
-      next_id = (uint32_t)T.capacity;
-      break;
-    }
-    // (f) partition the entries of split nodes into their children's segments
-    if (lds_cur)
-      partition_level<BLOCK, WIDE>(x, X.buf, lcur, n_chunks);
-    else
-      partition_level<BLOCK, WIDE>(x, X.buf, sc.cur, n_chunks);
-    __syncthreads();
-    // (g) the boundary between each pair of children, and their sums of w y^2
-    for (uint32_t r = tid; r < n_split; r += BLOCK) {
-      const Cursor c = lds_cur ? lcur[r] : sc.cur[r];
-      if (c.L == 0xFFFFFFFFu) continue;  // placed by its search
-      X.mend[2 * r] = c.L;
-      X.mstart[2 * r + 1] = c.L;
-      X.mQ[2 * r] = c.q;
-      X.mQ[2 * r + 1] -= c.q;
-    }
-    // the next level's tier counts and task queue head
-    if (tid < 3 + kSegClasses) sh.cnt[tid] = 0;
     if (tid == 0) {
       sh.next_task = NW;
-      if (GROUPED) sh.resume = 0;
+      sh.vi = vi + 1;
+      sh.vmin = m_v;
+      sh.vbase = nbase;
+      sh.resume = 1;
     }
     __syncthreads();
-    level_lo = next_id;
-    level_cnt = 2 * n_split;
-    next_id += 2 * n_split;
-    cur ^= 1;
-  }
-  // the tree of member max(vi, 0) is complete
-  work_rows = block_sum<BLOCK, uint64_t>(work_rows, sh.red);
-  work_nodes = block_sum<BLOCK, uint64_t>(work_nodes, sh.red);
-  work_part = block_sum<BLOCK, uint64_t>(work_part, sh.red);
-  work_hist = block_sum<BLOCK, uint64_t>(work_hist, sh.red);
-  const int vi = GROUPED ? sh.vi : 0, K = GROUPED ? sh.gk : 1;
-  const int64_t base_node = GROUPED ? sh.vbase : T.node_base;
-  const int v0 = vi < 0 ? 0 : vi;
-  // without a parting level every member's tree is the first one's
-  const int v1 = vi < 0 ? K : vi + 1;
-  for (int v = v0; v < v1; ++v) {
-    if (v > v0) {
-      const int64_t b = sh.gbase[v];
-      for (uint32_t i = tid; i < next_id; i += BLOCK) {
-        a.nodes[b + i] = a.nodes[base_node + i];
-        a.node_N[b + i] = a.node_N[base_node + i];
-      }
-    }
-    if (tid == 0) {
-      const int64_t ti = GROUPED ? sh.gtask[v] : sh.gtask[0];
-      a.n_nodes[ti] = (int32_t)next_id;
-      int64_t* wk = a.work + kWorkWords * ti;
-      const bool first = v == v0;
-      wk[0] = first ? (int64_t)work_rows : 0;
-      wk[1] = first ? (int64_t)work_nodes : 0;
-      wk[2] = first ? (int64_t)work_part : 0;
-      wk[3] = (int64_t)levels;
-      wk[4] = first ? (int64_t)work_hist : 0;
-    }
-  }
-  if (vi < 0 || vi + 1 == K) break;
-  // member vi + 1 grows on from the parting level's decisions: its searched
-  // state restored, the nodes of at most its min.node.size made leaves, the
-  // shared levels' node words copied into its slot
-  const int64_t nbase = sh.gbase[vi + 1], m_v = sh.gmin[vi + 1];
-  level_lo = sh.f_lo;
-  level_cnt = sh.f_cnt;
-  next_id = sh.f_next;
-  cur = (int)sh.f_cur;
-  levels = sh.f_levels;
-  work_rows = work_nodes = work_part = work_hist = 0;
-  {
-    const uint32_t f_big = sh.f_big, f_huge = sh.f_huge;
-    const int64_t b0 = sh.gbase[0];
-    for (uint32_t i = tid; i < level_lo; i += BLOCK) {
-      a.nodes[nbase + i] = a.nodes[b0 + i];
-      a.node_N[nbase + i] = a.node_N[b0 + i];
-    }
-    const Level2 C = cur ? sc.L1 : sc.L0;
-    const Level2 X = cur ? sc.L0 : sc.L1;
-    const uint32_t ni = sh.n_inbag;
-    for (uint32_t i = tid; i < ni; i += BLOCK) {
-      C.buf[i] = sc.SN.L.buf[i];
-      X.buf[i] = sc.SN.nbuf[i];
-    }
-    for (uint32_t k = tid; k < level_cnt; k += BLOCK) {
-      const uint32_t N = sc.SN.L.mN[k];
-      C.mstart[k] = sc.SN.L.mstart[k];
-      C.mend[k] = sc.SN.L.mend[k];
-      C.mN[k] = N;
-      C.mS[k] = sc.SN.L.mS[k];
-      C.mQ[k] = sc.SN.L.mQ[k];
-      const uint8_t st = sc.SN.status[k];
-      sc.status[k] = (int64_t)N <= m_v ? kLeaf : st;
-      sc.ridx[k] = sc.SN.ridx[k];
-      sc.dcol[k] = sc.SN.dcol[k];
-      sc.dbin[k] = sc.SN.dbin[k];
-      sc.dNL[k] = sc.SN.dNL[k];
-      sc.dSL[k] = sc.SN.dSL[k];
-      sc.dcnt[k] = sc.SN.dcnt[k];
-      sc.dQL[k] = sc.SN.dQL[k];
-    }
-    for (uint32_t i = tid; i < (f_big + f_huge) * (uint32_t)mtry; i += BLOCK) sc.recs[i] = sc.SN.recs[i];
-    if (WIDE && f_huge > 0) {
-      const uint4* src = reinterpret_cast<const uint4*>(sc.SN.side);
-      uint4* dst = reinterpret_cast<uint4*>(sc.side);
-      for (uint32_t i = tid; i < ni * (uint32_t)cand_stride(mtry) / 16u; i += BLOCK) dst[i] = src[i];
-    }
-    __syncthreads();  // (every thread has read the member index)
-    if (tid < 3 + kSegClasses) sh.cnt[tid] = tid == 1 ? f_big : tid == 2 ? f_huge : 0u;
-  }
-  if (tid == 0) {
-    sh.next_task = NW;
-    sh.vi = vi + 1;
-    sh.vmin = m_v;
-    sh.vbase = nbase;
-    sh.resume = 1;
-  }
-  __syncthreads();
   }
   (void)wid;
 }
