@@ -621,20 +621,26 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
       *reinterpret_cast<uint4*>(ho + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
     }
     // inclusive prefix sums of the B bins, ceil(B / 64) consecutive bins per lane
-    const int q = ((int)B + kWave - 1) / kWave;
-    const int b0 = lane * q;
-    uint64_t h[4];
-    uint64_t loc = 0;
+    if (B <= (uint32_t)kWave) {  // one bin per lane
+      const uint64_t h = lane < (int)B ? hv[lane] : 0ull;
+      const uint64_t v = wave_incl_scan<uint64_t>(h);
+      if (lane < (int)B) hv[lane] = v;
+    } else {
+      const int q = ((int)B + kWave - 1) / kWave;
+      const int b0 = lane * q;
+      uint64_t h[4];
+      uint64_t loc = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      h[u] = u < q && b0 + u < (int)B ? hv[b0 + u] : 0ull;
-      loc += h[u];
-    }
-    uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
+      for (int u = 0; u < 4; ++u) {
+        h[u] = u < q && b0 + u < (int)B ? hv[b0 + u] : 0ull;
+        loc += h[u];
+      }
+      uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v += h[u];
-      if (u < q && b0 + u < (int)B) hv[b0 + u] = v;
+      for (int u = 0; u < 4; ++u) {
+        v += h[u];
+        if (u < q && b0 + u < (int)B) hv[b0 + u] = v;
+      }
     }
     wave_lds_sync();
     if (valid) {
@@ -665,6 +671,24 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
 __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_t N, int64_t S, uint32_t& oNL,
                                               int64_t& oSL) {
   const int lane = (int)lane_id();
+  if (B <= kWave) {  // one bin per lane
+    const uint64_t h = lane < B ? hv[lane] : 0ull;
+    const uint64_t v = wave_incl_scan<uint64_t>(h);
+    double lbest = -1.0;
+    oNL = 0;
+    oSL = 0;
+    // an empty bin repeats the previous split, which already won any tie
+    if (h != 0 && lane <= B - 2) {
+      const uint32_t NL = packed_n(v);
+      if (NL < N) {
+        const int64_t SL = packed_s(v, NL);
+        lbest = split_score(SL, NL, S - SL, N - NL);
+        oNL = NL;
+        oSL = SL;
+      }
+    }
+    return wave_argmax_lane_ordered(lbest, lbest >= 0.0 ? lane : INT_MAX);
+  }
   const int q = (B + kWave - 1) / kWave;
   const int b0 = lane * q;
   uint64_t h[4];
