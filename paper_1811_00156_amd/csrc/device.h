@@ -19,6 +19,18 @@ struct U64x4 {
   uint64_t w[4];
 };
 
+// The 128-bit product a * b from four 32 x 32 -> 64-bit multiply-adds (the
+// schoolbook terms; no partial sum overflows 64 bits).
+__device__ __forceinline__ void mul_64x64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t t = (uint64_t)a0 * b0;
+  const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+  const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+  hi = (uint64_t)a1 * b1 + (u >> 32) + (v >> 32);
+  lo = (v << 32) | (uint32_t)t;
+}
+
 __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                                uint64_t k0, uint64_t k1) {
   constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
@@ -27,8 +39,9 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
-    const uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mul_64x64(c0, kM0, hi0, lo0);
+    mul_64x64(c2, kM1, hi1, lo1);
     const uint64_t n0 = hi1 ^ c1 ^ k0;
     const uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -45,8 +58,12 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 constexpr uint64_t kTagBootstrap = 0;
 constexpr uint64_t kTagMtry = 1;
 
-// Integer in [0, m) from a 64-bit draw: floor(r * m / 2^64).
-__device__ __forceinline__ uint64_t scale_draw(uint64_t r, uint64_t m) { return __umul64hi(r, m); }
+// Integer in [0, m) from a 64-bit draw: floor(r * m / 2^64), for m < 2^32:
+// floor((r1 m + floor(r0 m / 2^32)) / 2^32) with r = r1 2^32 + r0.
+__device__ __forceinline__ uint64_t scale_draw(uint64_t r, uint32_t m) {
+  const uint64_t t = (uint64_t)(uint32_t)r * m;
+  return ((uint64_t)(uint32_t)(r >> 32) * m + (t >> 32)) >> 32;
+}
 
 // ---------------------------------------------------------------------------
 // Row entry: one 64-bit word per in-bag row of a tree, moved by the partition.

@@ -319,7 +319,7 @@ __device__ __forceinline__ void draw_candidates(uint8_t* perm, int pst, uint64_t
     for (int w = 0; w < 4; ++w) {
       const int k = 4 * b + w;
       if (k < mtry) {
-        const int j = k + (int)scale_draw(r.w[w], (uint64_t)(C - k));
+        const int j = k + (int)scale_draw(r.w[w], (uint32_t)(C - k));
         const uint8_t vk = perm[k * pst], vj = perm[j * pst];
         perm[k * pst] = vj;
         perm[j * pst] = vk;
@@ -1093,7 +1093,7 @@ __device__ __forceinline__ void bootstrap_counts(const TreeTask& T, int64_t n, u
       const U64x4 r = philox4x64_10((uint64_t)b, kTagBootstrap, 0, (uint64_t)T.tree, T.seed, 0);
 #pragma unroll
       for (int w = 0; w < 4; ++w)
-        if (4 * b + w < n) atomicAdd(&cnt[scale_draw(r.w[w], (uint64_t)n)], 1u);
+        if (4 * b + w < n) atomicAdd(&cnt[scale_draw(r.w[w], (uint32_t)n)], 1u);
     }
     __syncthreads();
   }
