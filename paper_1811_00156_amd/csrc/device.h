@@ -112,14 +112,21 @@ __device__ __forceinline__ int64_t leaf_value(uint64_t N, int64_t S) {
 // Split score S_L^2/N_L + S_R^2/N_R: two products, two correctly rounded
 // divisions and one sum in binary64, in this order (the library is compiled
 // with -ffp-contract=off, so no fused multiply-add is formed).
+// (double)x for a 64-bit integer: h 2^32 + l with both halves converted exactly
+// and one rounding in the fused multiply-add, the correctly rounded value the
+// plain conversion gives, in three instructions instead of four.
+__device__ __forceinline__ double i64_to_f64(int64_t x) {
+  return __builtin_fma((double)(int32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+}
+
 __device__ __forceinline__ double split_score(int64_t SL, uint32_t NL, int64_t SR, uint32_t NR) {
-  const double a = (double)SL, b = (double)SR;
+  const double a = i64_to_f64(SL), b = i64_to_f64(SR);
   const double l = a * a / (double)NL;
   const double r = b * b / (double)NR;
   return l + r;
 }
 __device__ __forceinline__ double parent_score(int64_t S, uint64_t N) {
-  const double a = (double)S;
+  const double a = i64_to_f64(S);
   return a * a / (double)N;
 }
 
