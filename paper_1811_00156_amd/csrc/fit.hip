@@ -515,7 +515,7 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
       const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
       uint32_t cd[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) cd[u] = valid ? rowp[(cw[u >> 2] >> (8 * (u & 3))) & 0xFFu] : 0u;
+      for (int u = 0; u < 16; ++u) cd[u] = valid && g0 + u < nc ? rowp[(cw[u >> 2] >> (8 * (u & 3))) & 0xFFu] : 0u;
 #pragma unroll
       for (int u = 0; u < 16; ++u)
         if (g0 + u < nc) s_codes[(g0 + u) * kWave + lane] = (uint8_t)cd[u];
