@@ -119,15 +119,34 @@ __device__ __forceinline__ double i64_to_f64(int64_t x) {
   return __builtin_fma((double)(int32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
 }
 
+// a / b, correctly rounded, for a zero or in [1, 2^90] and b in [1, 2^20]: the
+// divide sequence the compiler emits for IEEE division (reciprocal, two Newton
+// steps, the quotient, one correction by fused multiply-add) without its
+// operand scaling and special-value fixup, which leave operands in these
+// ranges unchanged (no denormal, no overflow, no exponent gap near 768), so
+// the quotient is the same; 8 instructions instead of 11.  Checked against
+// IEEE division on 4.3e9 quotients of the split score's domain.
+__device__ __forceinline__ double div_pos(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double q = a * r;
+  const double rem = __builtin_fma(-b, q, a);
+  return __builtin_fma(rem, r, q);
+}
+
+// (|S| < 2^41 and N < 2^19 by the fixed-point budget: S^2 < 2^82.)
 __device__ __forceinline__ double split_score(int64_t SL, uint32_t NL, int64_t SR, uint32_t NR) {
   const double a = i64_to_f64(SL), b = i64_to_f64(SR);
-  const double l = a * a / (double)NL;
-  const double r = b * b / (double)NR;
+  const double l = div_pos(a * a, (double)NL);
+  const double r = div_pos(b * b, (double)NR);
   return l + r;
 }
 __device__ __forceinline__ double parent_score(int64_t S, uint64_t N) {
   const double a = i64_to_f64(S);
-  return a * a / (double)N;
+  return div_pos(a * a, (double)N);
 }
 
 // ---------------------------------------------------------------------------
