@@ -2,7 +2,7 @@
  * aiwc_rf_probe.h -- measurement probes of libaiwc_rf_probe.so (gfx950).
  *
  * Not part of the method: these calls measure hardware ceilings that the
- * tree-growing kernel is set against.  Its histogram build adds every in-bag row
+ * tree-growing kernel is set against, and check one of its arithmetic shortcuts.  Its histogram build adds every in-bag row
  * of a searched node to one packed 64-bit LDS bin per candidate column (the
  * per-node (count, sum) histograms of the variance-reduction split search that
  * the model of Sec. III-B needs), so besides HBM bandwidth its second ceiling is
@@ -36,6 +36,15 @@ extern "C" {
  * a null output pointer. */
 int aiwc_rf_probe_lds_add(int32_t width_bits, int32_t pattern, int32_t blocks, int32_t iters,
                           double* adds_per_s_host, double* elapsed_ms_host, void* stream);
+
+/* The tree-growing kernel's split-score division (a shortened IEEE divide
+ * sequence, valid for numerators that are zero or in [1, 2^90] and denominators
+ * in [1, 2^20]) against IEEE division, on `samples` quotients of the score's
+ * domain: the square of an integer of a random bit length up to 41 over an
+ * integer weight in [1, 2^18] or [1, 64], drawn from a counter hash of `seed`.
+ * mismatches_host: the quotients whose bit patterns differ (0 expected).
+ * EINVAL: samples outside [1, 2^40], a null output pointer. */
+int aiwc_rf_probe_divide(int64_t samples, uint64_t seed, uint64_t* mismatches_host, void* stream);
 
 /* Message of the calling thread's last failed probe call ("" after a success). */
 const char* aiwc_rf_probe_last_error(void);

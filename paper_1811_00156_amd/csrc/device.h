@@ -124,8 +124,8 @@ __device__ __forceinline__ double i64_to_f64(int64_t x) {
 // steps, the quotient, one correction by fused multiply-add) without its
 // operand scaling and special-value fixup, which leave operands in these
 // ranges unchanged (no denormal, no overflow, no exponent gap near 768), so
-// the quotient is the same; 8 instructions instead of 11.  Checked against
-// IEEE division on 4.3e9 quotients of the split score's domain.
+// the quotient is the same; 8 instructions instead of 11.  aiwc_rf_probe_divide
+// (libaiwc_rf_probe.so) checks it against IEEE division on that domain.
 __device__ __forceinline__ double div_pos(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   double e = __builtin_fma(-b, r, 1.0);

@@ -1,10 +1,12 @@
-// LDS atomic throughput probe (declared in include/aiwc_rf_probe.h): the
-// ceiling that the tree-growing kernel's LDS histogram adds are set against.
+// Measurement probes (declared in include/aiwc_rf_probe.h): the LDS atomic
+// throughput that the tree-growing kernel's histogram adds are set against,
+// and a check of the kernel's split-score division against IEEE division.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <string>
 
+#include "../device.h"
 #include "aiwc_rf.h"
 #include "aiwc_rf_probe.h"
 
@@ -62,7 +64,57 @@ int fail(int code, const std::string& m) {
   return code;
 }
 
+// A 64-bit finalizer (counter -> well-spread bits) for the check's operands.
+__host__ __device__ inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+// Quotient i of the split score's domain: the square of an integer of a random
+// bit length up to 41 (zero included) over an integer weight in [1, 2^18] (odd
+// lengths) or in [1, 64] (even lengths), by the kernel's division and by IEEE
+// division; differing bit patterns are counted.
+__global__ __launch_bounds__(256) void k_divide_check(uint64_t base, uint64_t seed, unsigned long long* bad) {
+  const uint64_t i = base + (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint64_t h1 = mix64(seed ^ (2 * i + 1)), h2 = mix64(seed ^ (2 * i + 2));
+  const int bits = (int)(h1 % 42u);
+  const int64_t a = bits == 0 ? 0 : (int64_t)((h1 >> 8) & ((1ull << bits) - 1u));
+  const uint32_t range = (bits & 1) ? 262144u : 64u;
+  const uint32_t n = 1u + (uint32_t)((h2 >> 5) % range);
+  const double ad = (double)a, num = ad * ad, den = (double)n;
+  const double q_ieee = num / den, q = aiwc::div_pos(num, den);
+  if (__double_as_longlong(q_ieee) != __double_as_longlong(q)) atomicAdd(bad, 1ull);
+}
+
 }  // namespace
+
+extern "C" int aiwc_rf_probe_divide(int64_t samples, uint64_t seed, uint64_t* mismatches_host, void* stream) {
+  if (!mismatches_host) return fail(AIWC_RF_EINVAL, "null pointer argument");
+  if (samples < 1 || samples > ((int64_t)1 << 40)) return fail(AIWC_RF_EINVAL, "samples must be in [1, 2^40]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  unsigned long long* bad = nullptr;
+  hipError_t e = hipMalloc((void**)&bad, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), s);
+  // launches of up to 2^28 quotients, rounded up to whole workgroups
+  const uint64_t mix = mix64((uint64_t)seed);
+  for (int64_t b = 0; e == hipSuccess && b < samples; b += (int64_t)1 << 28) {
+    const int64_t n = samples - b < ((int64_t)1 << 28) ? samples - b : ((int64_t)1 << 28);
+    k_divide_check<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((uint64_t)b, mix, bad);
+    e = hipGetLastError();
+  }
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (bad) (void)hipFree(bad);
+  if (e != hipSuccess) return fail(AIWC_RF_EHIP, std::string("HIP error: ") + hipGetErrorString(e));
+  *mismatches_host = h;
+  g_err.clear();
+  return AIWC_RF_OK;
+}
 
 extern "C" int aiwc_rf_probe_lds_add(int32_t width_bits, int32_t pattern, int32_t blocks, int32_t iters,
                                      double* adds_per_s_host, double* elapsed_ms_host, void* stream) {

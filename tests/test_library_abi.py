@@ -101,7 +101,7 @@ def test_probe_library_exports_its_header():
     plib = ctypes.CDLL(PROBE_LIB)
     text = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
     names = sorted(set(re.findall(r"\b(aiwc_rf_probe_[a-z0-9_]+)\s*\(", text)))
-    assert names == ["aiwc_rf_probe_last_error", "aiwc_rf_probe_lds_add"]
+    assert names == ["aiwc_rf_probe_divide", "aiwc_rf_probe_last_error", "aiwc_rf_probe_lds_add"]
     for name in names:
         assert hasattr(plib, name), f"{name} is declared in aiwc_rf_probe.h but not exported"
     P = ctypes.c_void_p
@@ -114,3 +114,9 @@ def test_probe_library_exports_its_header():
     assert b"width_bits" in plib.aiwc_rf_probe_last_error()
     assert plib.aiwc_rf_probe_lds_add(64, 2, 8, 10, ctypes.byref(r), ctypes.byref(ms), None) == -1
     assert plib.aiwc_rf_probe_lds_add(64, 0, 0, 10, ctypes.byref(r), ctypes.byref(ms), None) == -1
+    plib.aiwc_rf_probe_divide.argtypes = [ctypes.c_int64, ctypes.c_uint64, P, P]
+    n_bad = ctypes.c_uint64()
+    assert plib.aiwc_rf_probe_divide(0, 1, ctypes.byref(n_bad), None) == -1
+    assert b"samples" in plib.aiwc_rf_probe_last_error()
+    assert plib.aiwc_rf_probe_divide((1 << 40) + 1, 1, ctypes.byref(n_bad), None) == -1
+    assert plib.aiwc_rf_probe_divide(100, 1, None, None) == -1
