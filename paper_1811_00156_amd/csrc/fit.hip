@@ -428,12 +428,12 @@ __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node
 // (every code below 128): 128 + code - c stays in [1, 255] in each byte, so its
 // bit 7 is the comparison and no borrow crosses the bytes; otherwise per 16-bit
 // half, 256 + code - c stays in [1, 511] and bit 8 is the comparison.
-template <int W, bool C7>
+template <int W, bool C7, bool B3>
 __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* seg_codes, const uint8_t* seg_planes,
                                                 uint32_t& NL, int64_t& SL) {
   const uint32_t kk = C7 ? (code + 0x80u) * 0x01010101u : code * 0x00010001u + 0x01000100u;
-  uint32_t aN = 0, a0 = 0, a1 = 0, a2 = 0;
-  int32_t a3 = 0;
+  uint32_t aN = 0, a0 = 0, a1 = 0;
+  int32_t a2 = 0, a3 = 0;
 #pragma unroll 2
   for (int b4 = 0; b4 < W / 4; ++b4) {
     const uint32_t c4 = seg_codes[b4];
@@ -443,15 +443,23 @@ __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* s
     else
       ind = (((kk - (c4 & 0x00FF00FFu)) >> 8) & 0x00010001u) | ((kk - ((c4 >> 8) & 0x00FF00FFu)) & 0x01000100u);
     const uint4 pl = *reinterpret_cast<const uint4*>(seg_planes + b4 * 32);
-    const uint32_t p3 = *reinterpret_cast<const uint32_t*>(seg_planes + b4 * 32 + 16);
     aN = __builtin_amdgcn_udot4(ind, pl.x, aN, false);
     a0 = __builtin_amdgcn_udot4(ind, pl.y, a0, false);
     a1 = __builtin_amdgcn_udot4(ind, pl.z, a1, false);
-    a2 = __builtin_amdgcn_udot4(ind, pl.w, a2, false);
-    a3 = __builtin_amdgcn_sdot4((int32_t)ind, (int32_t)p3, a3, false);
+    if constexpr (B3) {
+      // w y in 24 bits: byte 2 is its signed top byte
+      a2 = __builtin_amdgcn_sdot4((int32_t)ind, (int32_t)pl.w, a2, false);
+    } else {
+      const uint32_t p3 = *reinterpret_cast<const uint32_t*>(seg_planes + b4 * 32 + 16);
+      a2 = (int32_t)__builtin_amdgcn_udot4(ind, pl.w, (uint32_t)a2, false);
+      a3 = __builtin_amdgcn_sdot4((int32_t)ind, (int32_t)p3, a3, false);
+    }
   }
   NL = aN;
-  SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)a2 << 16) + ((int64_t)a3 << 24);
+  if constexpr (B3)
+    SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)a2 << 16);
+  else
+    SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)(uint32_t)a2 << 16) + ((int64_t)a3 << 24);
 }
 
 template <int W>
@@ -479,9 +487,13 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   // of the wave fits a byte (bootstrap multiplicities nearly always do), as byte
   // planes: the group of rows 4j..4j+3 takes 32 bytes, word 0 their weights and
   // words 1..4 bytes 0..3 of their w y (|w y| < 2^30: two's complement, the top
-  // byte signed), so that four rows' left sums are five 4-byte dot products.
-  // Otherwise packed (w, w y) words, one per row.
+  // byte signed), so that four rows' left sums are five 4-byte dot products
+  // (four when every w y fits 24 bits).  Otherwise packed (w, w y) words, one
+  // per row.
   const bool bytes_ok = !a.wide_sums && __ballot(w > 255u) == 0ull;
+  // every w y of the wave fits 24 bits: its top byte is a sign extension, and
+  // three byte planes of w y carry it
+  const bool b3 = __ballot(wy < -(int64_t)(1 << 23) || wy >= (int64_t)(1 << 23)) == 0ull;
   // every column's codes fit 7 bits (at most 128 bins)
   const bool codes7 = a.bstride <= 128;
   uint8_t* planes = area;
@@ -530,9 +542,11 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
       int64_t SL;
       if (bytes_ok) {
         if (codes7)
-          byte_plane_sums<W, true>(code, seg_codes, seg_planes, NL, SL);
+          b3 ? byte_plane_sums<W, true, true>(code, seg_codes, seg_planes, NL, SL)
+             : byte_plane_sums<W, true, false>(code, seg_codes, seg_planes, NL, SL);
         else
-          byte_plane_sums<W, false>(code, seg_codes, seg_planes, NL, SL);
+          b3 ? byte_plane_sums<W, false, true>(code, seg_codes, seg_planes, NL, SL)
+             : byte_plane_sums<W, false, false>(code, seg_codes, seg_planes, NL, SL);
       } else {
         uint64_t acc = 0;  // packed left sums
 #pragma unroll 2

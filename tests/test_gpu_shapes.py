@@ -259,3 +259,34 @@ def test_small_node_sums_byte_planes_and_64_bit(setup, wide_sums, block, occ):
     g = fit_with(rf, ds, ob, env, params=rf.make_params(3, 7, 1, False, 4))
     for t, tree in enumerate(g.export()):
         assert_tree_equal(tree, ofn.tree(t), f"wide_sums {wide_sums} no bootstrap tree {t}")
+
+
+@pytest.mark.parametrize("bins", [64, 256])
+@pytest.mark.parametrize("block,occ", [("64", "5"), ("192", "6")])
+def test_small_node_sums_wide_responses(setup, bins, block, occ):
+    """Responses ten times wider (log10 times in [-59, -7]): with bootstrap
+    weights of 3 and more, w y no longer fits 24 bits in many waves, so the
+    small-node searches take both the four- and the five-plane byte sums (and,
+    at 64 bins, the 7-bit code comparisons); the trees equal the oracle's."""
+    rf, ds, ob, of = setup
+    from oracle import oracle as O
+
+    y10 = np.ascontiguousarray(ds.y * 10.0)
+    assert np.abs(y10).max() < 64.0
+    obb = O.bin(ds.X, ds.device, ds.n_devices, bins)
+    ofb = O.fit(obb.codes, obb.n_bins, y10, 4, 5, 1, seed=23)
+    env = {"AIWC_RF_GROW_BLOCK": block, "AIWC_RF_GROW_OCC": occ, "AIWC_RF_HUGE_MIN": "100000"}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        binner = rf.aiwc_rf_binner_from_counts(obb.n_bins)
+        f = rf.aiwc_rf_fit(to_dev(obb.codes), binner, to_dev(y10), rf.make_params(4, 5, 1, True, 23))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    log(f"wide responses bins={bins} block={block}")
+    for t, tree in enumerate(f.export()):
+        assert_tree_equal(tree, ofb.tree(t), f"wide responses bins {bins} block {block} tree {t}")
