@@ -377,6 +377,17 @@ __device__ __forceinline__ uint64_t pack_ns(uint32_t w, int64_t wy) { return ((u
 __device__ __forceinline__ uint32_t packed_n(uint64_t v) { return (uint32_t)((v + (1ull << 44)) >> 45); }
 __device__ __forceinline__ int64_t packed_s(uint64_t v, uint32_t n) { return (int64_t)(v - ((uint64_t)n << 45)); }
 
+// Inclusive wave scan of packed bins of a node that weighs below 512: every
+// prefix of its weights fits 9 bits and of its sums 32 bits (|y_fp| <= 2^22),
+// so the two are scanned as 32-bit words (one DPP add a step) and packed again.
+__device__ __forceinline__ uint64_t scan_packed_small(uint64_t h) {
+  const uint32_t n = packed_n(h);
+  const int32_t s = (int32_t)packed_s(h, n);
+  const uint32_t pn = wave_incl_scan_u32(n);
+  const int32_t ps = (int32_t)wave_incl_scan_u32((uint32_t)s);
+  return pack_ns(pn, ps);
+}
+
 // The end of a small node's search, for the W lanes of its segment (one row
 // each, lane `sbase + r`): the left child's weight, sum and sum of w y^2 from
 // segment reductions, and the node's rows placed into its children's segments
@@ -637,8 +648,7 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
     // inclusive prefix sums of the B bins, ceil(B / 64) consecutive bins per lane
     if (B <= (uint32_t)kWave) {  // one bin per lane
       const uint64_t h = lane < (int)B ? hv[lane] : 0ull;
-      const uint64_t v = wave_incl_scan<uint64_t>(h);
-      if (lane < (int)B) hv[lane] = v;
+      if (lane < (int)B) hv[lane] = N < 512u ? scan_packed_small(h) : wave_incl_scan<uint64_t>(h);
     } else {
       const int q = ((int)B + kWave - 1) / kWave;
       const int b0 = lane * q;
@@ -687,7 +697,7 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
   const int lane = (int)lane_id();
   if (B <= kWave) {  // one bin per lane
     const uint64_t h = lane < B ? hv[lane] : 0ull;
-    const uint64_t v = wave_incl_scan<uint64_t>(h);
+    const uint64_t v = N < 512u ? scan_packed_small(h) : wave_incl_scan<uint64_t>(h);
     double lbest = -1.0;
     oNL = 0;
     oSL = 0;
