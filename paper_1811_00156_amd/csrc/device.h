@@ -144,6 +144,15 @@ __device__ __forceinline__ double split_score(int64_t SL, uint32_t NL, int64_t S
   const double r = div_pos(b * b, (double)NR);
   return l + r;
 }
+// The same score for a node that weighs below 512: |S_L|, |S_R| < 511 * 2^22 <
+// 2^31, so each converts exactly from 32 bits (one conversion instead of
+// i64_to_f64's three) to the same double.
+__device__ __forceinline__ double split_score32(int32_t SL, uint32_t NL, int32_t SR, uint32_t NR) {
+  const double a = (double)SL, b = (double)SR;
+  const double l = div_pos(a * a, (double)NL);
+  const double r = div_pos(b * b, (double)NR);
+  return l + r;
+}
 __device__ __forceinline__ double parent_score(int64_t S, uint64_t N) {
   const double a = i64_to_f64(S);
   return div_pos(a * a, (double)N);

@@ -434,11 +434,16 @@ __device__ __forceinline__ void small_finish(const Ctx& x, uint32_t k, bool node
 
 // Left sums of the split at `code` over a segment of W rows staged as byte
 // planes (the group of rows 4j..4j+3 takes 32 bytes: word 0 their weights,
-// words 1..4 bytes 0..3 of their w y), four rows at a time: byte b of `ind` is
-// 1 when row b's code is <= `code`, then dot products with the planes.  C7
-// (every code below 128): 128 + code - c stays in [1, 255] in each byte, so its
-// bit 7 is the comparison and no borrow crosses the bytes; otherwise per 16-bit
-// half, 256 + code - c stays in [1, 511] and bit 8 is the comparison.
+// words 1..4 bytes 0..3 of their w y), four rows at a time: byte b of `ind`
+// marks row b's code <= `code`, then dot products with the planes.  C7 (every
+// code below 128): 128 + code - c stays in [1, 255] in each byte, so no borrow
+// crosses the bytes and its bit 7 is the comparison; `ind` keeps that bit in
+// place (byte 0x80: 128 unsigned, -128 signed), so the sums come out times 128
+// (the signed top plane's times -128) and one exact shift at the end divides it
+// out.  Otherwise per 16-bit half 256 + code - c stays in [1, 511] and its high
+// byte (0 or 1) is the comparison: bytes 0 and 2 of the codes are compared in
+// place, bytes 1 and 3 moved down by a byte permute, and a second permute
+// gathers the four high bytes.
 template <int W, bool C7, bool B3>
 __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* seg_codes, const uint8_t* seg_planes,
                                                 uint32_t& NL, int64_t& SL) {
@@ -449,10 +454,13 @@ __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* s
   for (int b4 = 0; b4 < W / 4; ++b4) {
     const uint32_t c4 = seg_codes[b4];
     uint32_t ind;
-    if constexpr (C7)
-      ind = ((kk - c4) >> 7) & 0x01010101u;
-    else
-      ind = (((kk - (c4 & 0x00FF00FFu)) >> 8) & 0x00010001u) | ((kk - ((c4 >> 8) & 0x00FF00FFu)) & 0x01000100u);
+    if constexpr (C7) {
+      ind = (kk - c4) & 0x80808080u;
+    } else {
+      const uint32_t d02 = kk - (c4 & 0x00FF00FFu);
+      const uint32_t d13 = kk - __builtin_amdgcn_perm(0u, c4, 0x0c030c01u);  // bytes 1, 3 of c4 to 0, 2
+      ind = __builtin_amdgcn_perm(d02, d13, 0x03070105u);  // bytes 1, 3 of each difference, interleaved
+    }
     const uint4 pl = *reinterpret_cast<const uint4*>(seg_planes + b4 * 32);
     aN = __builtin_amdgcn_udot4(ind, pl.x, aN, false);
     a0 = __builtin_amdgcn_udot4(ind, pl.y, a0, false);
@@ -466,11 +474,22 @@ __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* s
       a3 = __builtin_amdgcn_sdot4((int32_t)ind, (int32_t)p3, a3, false);
     }
   }
-  NL = aN;
-  if constexpr (B3)
-    SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)a2 << 16);
-  else
-    SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)(uint32_t)a2 << 16) + ((int64_t)a3 << 24);
+  if constexpr (C7) {
+    // every accumulator is a multiple of 128 (at most 128 * 255 * 32): byte
+    // plane j's sum times 2^(8 j) is a_j / 128 * 2^(8 j), the signed top
+    // plane's negated
+    NL = aN >> 7;
+    if constexpr (B3)
+      SL = (int64_t)(a0 >> 7) + ((int64_t)a1 << 1) - ((int64_t)a2 << 9);
+    else
+      SL = (int64_t)(a0 >> 7) + ((int64_t)a1 << 1) + ((int64_t)(uint32_t)a2 << 9) - ((int64_t)a3 << 17);
+  } else {
+    NL = aN;
+    if constexpr (B3)
+      SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)a2 << 16);
+    else
+      SL = (int64_t)a0 + ((int64_t)a1 << 8) + ((int64_t)(uint32_t)a2 << 16) + ((int64_t)a3 << 24);
+  }
 }
 
 template <int W>
@@ -507,6 +526,8 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   const bool b3 = __ballot(wy < -(int64_t)(1 << 23) || wy >= (int64_t)(1 << 23)) == 0ull;
   // every column's codes fit 7 bits (at most 128 bins)
   const bool codes7 = a.bstride <= 128;
+  // every node of the wave weighs below 512: its sums fit 32 bits
+  const bool light = __ballot(N >= 512u) == 0ull;
   uint8_t* planes = area;
   uint64_t* s_pv = reinterpret_cast<uint64_t*>(area);
   if (bytes_ok) {
@@ -570,7 +591,8 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
         SL = packed_s(acc, NL);
       }
       if (valid && NL < N) {
-        const double sc = split_score(SL, NL, S - SL, N - NL);
+        const double sc = light ? split_score32((int32_t)SL, NL, (int32_t)S - (int32_t)SL, N - NL)
+                                : split_score(SL, NL, S - SL, N - NL);
         if (sc > best) {
           best = sc;
           best_ib = ((uint32_t)(i0 + i) << 8) | code;
@@ -672,7 +694,8 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
       const uint32_t NL = packed_n(V);
       if (NL < N) {
         const int64_t SL = packed_s(V, NL);
-        const double sc = split_score(SL, NL, S - SL, N - NL);
+        const double sc = N < 512u ? split_score32((int32_t)SL, NL, (int32_t)S - (int32_t)SL, N - NL)
+                                   : split_score(SL, NL, S - SL, N - NL);
         if (sc > best) {
           best = sc;
           best_ib = (i << 8) | (int32_t)code;
@@ -706,7 +729,8 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
       const uint32_t NL = packed_n(v);
       if (NL < N) {
         const int64_t SL = packed_s(v, NL);
-        lbest = split_score(SL, NL, S - SL, N - NL);
+        lbest = N < 512u ? split_score32((int32_t)SL, NL, (int32_t)S - (int32_t)SL, N - NL)
+                         : split_score(SL, NL, S - SL, N - NL);
         oNL = NL;
         oSL = SL;
       }
@@ -722,7 +746,7 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
     h[u] = u < q && b0 + u < B ? hv[b0 + u] : 0ull;
     loc += h[u];
   }
-  uint64_t v = wave_incl_scan<uint64_t>(loc) - loc;
+  uint64_t v = (N < 512u ? scan_packed_small(loc) : wave_incl_scan<uint64_t>(loc)) - loc;
   double lbest = -1.0;
   int32_t lbin = INT_MAX;
   oNL = 0;
@@ -736,7 +760,8 @@ __device__ __forceinline__ ArgMax scan_packed(const uint64_t* hv, int B, uint32_
     const uint32_t NL = packed_n(v);
     if (b <= B - 2 && NL < N) {
       const int64_t SL = packed_s(v, NL);
-      const double s = split_score(SL, NL, S - SL, N - NL);
+      const double s = N < 512u ? split_score32((int32_t)SL, NL, (int32_t)S - (int32_t)SL, N - NL)
+                                : split_score(SL, NL, S - SL, N - NL);
       if (s > lbest) {
         lbest = s;
         lbin = b;
