@@ -159,6 +159,23 @@ __device__ __forceinline__ double parent_score(int64_t S, uint64_t N) {
 }
 
 // ---------------------------------------------------------------------------
+// Loads through global-address-space pointers.  Pointers the kernel carves
+// out of its scratch area are generic, and a generic (flat) load counts
+// against the LDS counter as well as the memory counter, so a wait for an LDS
+// result also waits for it.  A 16-byte load goes through a native vector type
+// (a copy of uint4 would read through a generic reference).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gload16(const void* p) {
+  const u32x4_t v = *(const __attribute__((address_space(1))) u32x4_t*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// ---------------------------------------------------------------------------
 // Wave64 collectives.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

@@ -553,16 +553,22 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
   for (int i0 = 0; i0 < mtry; i0 += kWave) {
     const int nc = min(kWave, mtry - i0);
     // gather the row's codes in every candidate column of this chunk at once:
-    // sixteen candidates per 16-byte load, sixteen gathers in flight
+    // sixteen candidates per 16-byte load, sixteen gathers in flight.  Every
+    // lane loads and stores without a branch: a lane without a row reads row 0
+    // (entry 0), whose codes no sum uses (its weight and w y are zero), and a
+    // position past the chunk reads column 0 into a slot no candidate reads
+    // (g0 + u < 64: inside the 64-column staging area).
     for (int g0 = 0; g0 < nc; g0 += 16) {
-      const uint4 c16 = *reinterpret_cast<const uint4*>(cand + i0 + g0);
+      const uint4 c16 = gload16(cand + i0 + g0);
       const uint32_t cw[4] = {c16.x, c16.y, c16.z, c16.w};
       uint32_t cd[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) cd[u] = valid && g0 + u < nc ? rowp[(cw[u >> 2] >> (8 * (u & 3))) & 0xFFu] : 0u;
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t c = g0 + u < nc ? (cw[u >> 2] >> (8 * (u & 3))) & 0xFFu : 0u;
+        cd[u] = gload(rowp + c);
+      }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (g0 + u < nc) s_codes[(g0 + u) * kWave + lane] = (uint8_t)cd[u];
+      for (int u = 0; u < 16; ++u) s_codes[(g0 + u) * kWave + lane] = (uint8_t)cd[u];
     }
     wave_lds_sync();
     for (int i = 0; i < nc; ++i) {
@@ -635,7 +641,12 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   uint8_t* area = reinterpret_cast<uint8_t*>(&wl);
   uint64_t* hb = reinterpret_cast<uint64_t*>(area);  // [2][256] packed bins, then prefix sums
   uint8_t* s_cand = area + 4096;                     // [mtry]
-  for (int i = lane; i < mtry; i += kWave) s_cand[i] = cand[i];
+  uint8_t* s_bm1 = area + 4352;                      // [mtry]: each candidate's bin count - 1
+  for (int i = lane; i < mtry; i += kWave) {
+    const uint32_t c = gload(cand + i);
+    s_cand[i] = (uint8_t)c;
+    s_bm1[i] = (uint8_t)(gload(a.n_bins + c) - 1);
+  }
   // both buffers start zeroed: four bins per lane each
   *reinterpret_cast<uint4*>(hb + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
   *reinterpret_cast<uint4*>(hb + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
@@ -648,14 +659,16 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   // the end
   double best = -1.0;
   int32_t best_ib = INT_MAX;
+  // every lane fetches its code (a lane without a row reads row 0, entry 0, and
+  // adds nothing), so that the fetch is not a branch the memory wait must close
   uint32_t c_next = rfl(s_cand[0]);
-  uint32_t code_next = valid ? rowp[c_next] : 0u;
+  uint32_t code_next = gload(rowp + c_next);
   for (int i = 0; i < mtry; ++i) {
     const uint32_t code = code_next;
-    const uint32_t B = (uint32_t)a.n_bins[c_next];  // this candidate column's bins
+    const uint32_t B = rfl(s_bm1[i]) + 1u;  // this candidate column's bins
     if (i + 1 < mtry) {  // fetch the next column's codes while this one is scanned
       c_next = rfl(s_cand[i + 1]);
-      code_next = valid ? rowp[c_next] : 0u;
+      code_next = gload(rowp + c_next);
     }
     uint64_t* hv = hb + (i & 1) * 256;
     if (valid) atomicAdd((unsigned long long*)&hv[code], (unsigned long long)pv);
@@ -805,11 +818,13 @@ __device__ __forceinline__ void big_task(const Ctx& x, uint32_t j, int ci0, Wave
     uint32_t code[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) e[u] = p0 + u * kWave < end ? x.buf[p0 + u * kWave] : 0ull;
+    // every lane loads the task's gn codes under a wave-uniform condition only:
+    // past the node's end the entry is 0 (row 0), whose codes are not added
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint8_t* rp = a.rcodes + (size_t)entry_row(e[u]) * a.rC;
 #pragma unroll
-      for (int g = 0; g < G; ++g) code[u][g] = (g < gn && p0 + u * kWave < end) ? rp[c[g]] : 0u;
+      for (int g = 0; g < G; ++g) code[u][g] = g < gn ? gload(rp + c[g]) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
