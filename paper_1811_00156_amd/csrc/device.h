@@ -225,6 +225,14 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
 }
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) { return wave_incl_scan<uint32_t>(v); }
 
+// v of lane `src` (per lane) by two LDS-crossbar permutes; every lane active.
+__device__ __forceinline__ uint64_t lane_pick64(uint64_t v, uint32_t src) {
+  const int addr = (int)(src << 2);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T read_lane(T v, int l) {
   if constexpr (sizeof(T) == 8) {

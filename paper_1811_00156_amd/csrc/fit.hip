@@ -620,8 +620,11 @@ __device__ __forceinline__ void small_task(const Ctx& x, const NodeDesc* list, u
 // prefix scan over the bins (ceil(B / 64) per lane) turns them into left sums,
 // and every lane scores the split at its own row's code (rows with the largest
 // code leave the right side empty and are skipped; lanes sharing a code score
-// the same split).  Two bin buffers alternate between candidates, so that the
-// previous candidate's bins are cleared while this one is scanned.
+// the same split).  A column of at most 64 bins keeps its prefix sums in
+// registers (one bin per lane, read and cleared by its lane) and each lane
+// takes the one at its own code by a cross-lane read; a wider column writes
+// them back to LDS.  Two bin buffers alternate between candidates, so that a
+// wider column's bins are cleared while the next candidate is scanned.
 __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, uint32_t t, uint32_t n_list, WaveHist& wl) {
   const GrowArgs& a = *x.a;
   const int mtry = x.T->mtry;
@@ -663,6 +666,7 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
   // adds nothing), so that the fetch is not a branch the memory wait must close
   uint32_t c_next = rfl(s_cand[0]);
   uint32_t code_next = gload(rowp + c_next);
+  bool prev_in_lds = false;  // the previous candidate left prefix sums in its buffer
   for (int i = 0; i < mtry; ++i) {
     const uint32_t code = code_next;
     const uint32_t B = rfl(s_bm1[i]) + 1u;  // this candidate column's bins
@@ -673,18 +677,26 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
     uint64_t* hv = hb + (i & 1) * 256;
     if (valid) atomicAdd((unsigned long long*)&hv[code], (unsigned long long)pv);
     wave_lds_sync();
-    // the previous candidate's buffer is free again (every lane read its left
-    // sums before these adds): clear it while this one is scanned
-    if (i > 0) {
+    // a previous candidate whose prefix sums went to LDS left its buffer dirty;
+    // every lane read its left sums before these adds: clear it while this one
+    // is scanned
+    if (prev_in_lds) {
       uint64_t* ho = hb + ((i - 1) & 1) * 256;
       *reinterpret_cast<uint4*>(ho + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
       *reinterpret_cast<uint4*>(ho + 4 * lane + 2) = make_uint4(0u, 0u, 0u, 0u);
     }
-    // inclusive prefix sums of the B bins, ceil(B / 64) consecutive bins per lane
-    if (B <= (uint32_t)kWave) {  // one bin per lane
+    uint64_t V;  // left sums (packed) of the split at this lane's code
+    if (B <= (uint32_t)kWave) {
+      // one bin per lane: the lane owning bin b reads and clears it (the buffer
+      // is zero again for its next use), the prefix sums stay in registers,
+      // and each lane takes the one at its own code by a cross-lane read
       const uint64_t h = lane < (int)B ? hv[lane] : 0ull;
-      if (lane < (int)B) hv[lane] = N < 512u ? scan_packed_small(h) : wave_incl_scan<uint64_t>(h);
+      if (lane < (int)B) hv[lane] = 0ull;
+      const uint64_t v = N < 512u ? scan_packed_small(h) : wave_incl_scan<uint64_t>(h);
+      V = lane_pick64(v, code);
+      prev_in_lds = false;
     } else {
+      // inclusive prefix sums of the B bins, ceil(B / 64) consecutive bins per lane
       const int q = ((int)B + kWave - 1) / kWave;
       const int b0 = lane * q;
       uint64_t h[4];
@@ -700,10 +712,11 @@ __device__ __forceinline__ void rank_task(const Ctx& x, const NodeDesc* list, ui
         v += h[u];
         if (u < q && b0 + u < (int)B) hv[b0 + u] = v;
       }
+      wave_lds_sync();
+      V = hv[code];  // code < B for every lane (a lane without a row has row 0's)
+      prev_in_lds = true;
     }
-    wave_lds_sync();
     if (valid) {
-      const uint64_t V = hv[code];
       const uint32_t NL = packed_n(V);
       if (NL < N) {
         const int64_t SL = packed_s(V, NL);
