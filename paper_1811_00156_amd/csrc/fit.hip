@@ -450,7 +450,7 @@ __device__ __forceinline__ void byte_plane_sums(uint32_t code, const uint32_t* s
   const uint32_t kk = C7 ? (code + 0x80u) * 0x01010101u : code * 0x00010001u + 0x01000100u;
   uint32_t aN = 0, a0 = 0, a1 = 0;
   int32_t a2 = 0, a3 = 0;
-#pragma unroll 2
+#pragma unroll 4
   for (int b4 = 0; b4 < W / 4; ++b4) {
     const uint32_t c4 = seg_codes[b4];
     uint32_t ind;
